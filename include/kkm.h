@@ -1,0 +1,193 @@
+/*
+ * kkm.h — C ABI of the MI355X (gfx950) Kernel K-means library, libkkm.so.
+ *
+ * The method (paper: "Popcorn: Accelerating Kernel K-means on GPUs through
+ * Sparse Linear Algebra", PPoPP'25):
+ *
+ *   K = kappa(P P^T) once (Sec. 3.2, Algorithm 2 first step), then per
+ *   iteration (Algorithm 2 loop body, Eq. dist_sp_1 and Eq. cnorms_gemv)
+ *     E = K V^T                 SpMM with the k x n selection matrix V
+ *                               (Eq. v_init: V_ci = 1/|c| if a(i) = c)
+ *     ||c_c||^2 = (V z)_c       SpMV with z_i = E_{i,a(i)}
+ *     D_ic = K_ii - 2 E_ic + ||c_c||^2
+ *     a'(i) = argmin_c D_ic
+ *   until no label changes or maxiter steps ran (Algorithm 1).
+ *
+ * Conventions for every entry point
+ *  - Array arguments are DEVICE pointers owned by the caller unless a comment
+ *    says "host".  Matrices are row-major with an explicit leading dimension
+ *    (in elements).  The library never frees caller memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  kkm_gram and
+ *    kkm_iterate only enqueue work on it and return at once; their scalar
+ *    results are written to device memory.  kkm_fit and kkm_fit_ex
+ *    synchronise the stream before returning.
+ *  - Calls return a kkm_status and never abort or throw.  On an error the
+ *    outputs are unspecified and kkm_last_error() describes the cause
+ *    (thread-local, valid until the next call on the same thread).
+ *  - Labels are int32 cluster indices in [0, k).
+ *  - Kernel functions (Sec. 3.2; sigma of the Gaussian is folded into gamma):
+ *      KKM_LINEAR  kappa(x,y) = x.y
+ *      KKM_POLY    kappa(x,y) = (gamma x.y + coef0)^degree,  degree >= 1
+ *      KKM_GAUSS   kappa(x,y) = exp(-gamma ||x - y||^2),     gamma > 0
+ *  - Empty clusters (|c| = 0, where V's row and the centroid are undefined):
+ *      KKM_EMPTY_INF            D_ic = +inf, the cluster stays empty
+ *      KKM_EMPTY_ZERO_CENTROID  D_ic = K_ii (V's row of zeros taken literally:
+ *                               a centroid at the feature-space origin)
+ *    argmin ties go to the lowest cluster index.
+ */
+#ifndef KKM_H
+#define KKM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KKM_OK = 0,
+    KKM_ERR_ARG = -1,         /* a size, pointer or parameter is invalid        */
+    KKM_ERR_LABEL = -2,       /* an input label lies outside [0, k)             */
+    KKM_ERR_NOMEM = -3,       /* a device allocation or a workspace is too small */
+    KKM_ERR_HIP = -4,         /* the HIP runtime reported an error               */
+    KKM_ERR_UNSUPPORTED = -5, /* valid request this build does not implement    */
+    KKM_ERR_NONFINITE = -6    /* the kernel matrix has a non-finite diagonal     */
+} kkm_status;
+
+typedef enum { KKM_LINEAR = 0, KKM_POLY = 1, KKM_GAUSS = 2 } kkm_kernel_type;
+
+/* Element types: arithmetic of the Gram product / storage of K. */
+typedef enum { KKM_F32 = 0, KKM_BF16 = 1, KKM_FP8_ROWSCALED = 2 } kkm_dtype;
+
+typedef enum { KKM_EMPTY_INF = 0, KKM_EMPTY_ZERO_CENTROID = 1 } kkm_empty_policy;
+
+/* Largest k supported by the per-iteration kernels (LDS histogram size). */
+#define KKM_MAX_K 1024
+
+/*
+ * kkm_gram — kernel matrix K = kappa(P P^T) and its diagonal (Sec. 3.2 and
+ * Sec. 4.2: B = P P^T by a dense product, the kernel function applied to each
+ * entry, diag(K) extracted; here all three are one pass, with the product on
+ * MFMA and the kernel function and diagonal in its epilogue).
+ *
+ *   X       [n, ldx] float32 points, row-major (d features used per row).
+ *   n, d    number of points (>= 1) and features (>= 1); ldx >= d.
+ *   kernel_type, gamma, coef0, degree   kernel function (see above).
+ *   gram_prec  arithmetic of the product: KKM_F32 (FP32 MFMA), KKM_BF16
+ *           (inputs rounded to bfloat16, FP32 accumulation) or
+ *           KKM_FP8_ROWSCALED (each row scaled by max|x|/448 and rounded to
+ *           OCP FP8 E4M3, FP32 accumulation).  Squared norms for the Gaussian
+ *           are taken from the same rounded values the product uses.
+ *   k_store element type of K: KKM_F32 or KKM_BF16.
+ *   K       [n, ldk] output, ldk >= n; both triangles are written and K is
+ *           exactly symmetric.  With KKM_F32 storage, ldk*4 bytes per row.
+ *   diagK   [n] float32 output, K_ii (exactly 1 for the Gaussian).
+ *   ws, ws_bytes  device workspace of at least
+ *           kkm_gram_workspace_bytes(n, d, gram_prec) bytes (may be NULL
+ *           when that is 0).
+ * Errors: KKM_ERR_ARG for bad sizes/params/NULL outputs, KKM_ERR_NOMEM for a
+ * small workspace, KKM_ERR_UNSUPPORTED for an unimplemented precision pair.
+ */
+kkm_status kkm_gram(const float *X, int64_t n, int64_t d, int64_t ldx,
+                    int32_t kernel_type, double gamma, double coef0, int32_t degree,
+                    int32_t gram_prec, int32_t k_store,
+                    void *K, int64_t ldk, float *diagK,
+                    void *ws, size_t ws_bytes, void *stream);
+
+size_t kkm_gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec);
+
+/*
+ * kkm_iterate — one reassignment step (Algorithm 2 loop body) for labels_in:
+ * builds V in CSR form from the labels (Sec. 4.1), E = K V^T by a row sweep of
+ * K (Eq. dist_sp_1), the centroid norms diag(V K V^T) = V z (Eq. c_norm,
+ * Eq. cnorms_gemv), D = K_ii - 2E + ||c||^2 and the argmin with the new
+ * cluster sizes, all on the GPU.  Stateless: resume = call again.
+ *
+ *   K, k_store, ldk   kernel matrix from kkm_gram (n x n, row stride ldk).
+ *   diagK      [n] float32, K_ii.
+ *   n, k       points and clusters, 1 <= k <= min(n, KKM_MAX_K).
+ *   labels_in  [n] int32 current labels (not modified).
+ *   empty_policy  KKM_EMPTY_INF or KKM_EMPTY_ZERO_CENTROID.
+ *   labels_out [n] int32 new labels (must not alias labels_in).
+ *   counts_out [k] int32 cluster sizes of labels_out.
+ *   n_changed  [1] int64 number of i with labels_out[i] != labels_in[i];
+ *              -1 if a label of labels_in lies outside [0, k) (the step is
+ *              then skipped and the other outputs are unspecified).
+ *   J_in       [1] double objective of labels_in:
+ *              sum_i ||phi(x_i) - mu_{a(i)}||^2 = sum_i D_{i, labels_in(i)}.
+ *   D_out      [n, k] float32 distances, nullable (for checking).
+ *   ctilde_out [k] float32 centroid norms ||c_c||^2, nullable (0 for empty).
+ *   ws, ws_bytes  device workspace of at least kkm_iterate_workspace_bytes(n, k).
+ * The result is deterministic: the same inputs give bitwise the same outputs.
+ */
+kkm_status kkm_iterate(const void *K, int32_t k_store, int64_t ldk, const float *diagK,
+                       int64_t n, int32_t k, const int32_t *labels_in, int32_t empty_policy,
+                       int32_t *labels_out, int32_t *counts_out, int64_t *n_changed,
+                       double *J_in, float *D_out, float *ctilde_out,
+                       void *ws, size_t ws_bytes, void *stream);
+
+size_t kkm_iterate_workspace_bytes(int64_t n, int32_t k);
+
+/*
+ * kkm_fit — the whole method (Algorithm 2): K once, then steps until no label
+ * changes (check_convergence != 0) or max_iter steps ran.
+ *
+ *   X, n, d, ldx, kernel_type, gamma, coef0, degree   as kkm_gram.
+ *   k          clusters, 1 <= k <= min(n, KKM_MAX_K).
+ *   labels0    [n] int32 initial labels (the paper draws them uniformly at
+ *              random; the caller supplies them).
+ *   max_iter   >= 0; 0 returns labels0 and its objective.
+ *   labels_out [n] int32 final labels (device).
+ *   objective  host double: J of labels_out (FP64 reduction on the GPU).
+ *   iters      host int32: steps executed, including a last step that
+ *              changed nothing.
+ *   K_ws       device buffer for K of at least n*ldk*4 bytes, or NULL to let
+ *              the library allocate (and free) it.  ldk >= n is used with K_ws;
+ *              it is ignored when K_ws is NULL.
+ * Errors: as kkm_gram and kkm_iterate, plus KKM_ERR_LABEL for labels0 outside
+ * [0, k) and KKM_ERR_NONFINITE when diag(K) has a NaN or infinity.
+ */
+kkm_status kkm_fit(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t k,
+                   int32_t kernel_type, double gamma, double coef0, int32_t degree,
+                   const int32_t *labels0, int32_t max_iter, int32_t check_convergence,
+                   int32_t *labels_out, double *objective, int32_t *iters,
+                   void *K_ws, int64_t ldk, void *stream);
+
+/*
+ * kkm_fit_ex — kkm_fit with the precision forms and per-run records.
+ *
+ *   gram_prec, k_store, empty_policy   as kkm_gram / kkm_iterate.
+ *   J_trace       host double [max_iter + 1], nullable: J of the labels
+ *                 entering each executed step, then J(labels_out).
+ *   changed_trace host int64 [max_iter], nullable: labels changed per step.
+ *   times_ms      host double [3], nullable: {Gram, all steps, final objective}
+ *                 wall time on the stream, in milliseconds.
+ */
+kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t k,
+                      int32_t kernel_type, double gamma, double coef0, int32_t degree,
+                      int32_t gram_prec, int32_t k_store, int32_t empty_policy,
+                      const int32_t *labels0, int32_t max_iter, int32_t check_convergence,
+                      int32_t *labels_out, double *objective, int32_t *iters,
+                      void *K_ws, int64_t ldk, double *J_trace, int64_t *changed_trace,
+                      double *times_ms, void *stream);
+
+/*
+ * Launch timing for benchmarks (process-wide).  kkm_timing_enable(1) clears
+ * the records and starts bracketing every Gram launch, every SpMM sweep launch
+ * and every whole kkm_iterate step with HIP events on the caller's stream;
+ * kkm_timing_enable(0) clears and stops.  kkm_timing_read waits for the
+ * recorded events and returns, per class {0: Gram, 1: sweep, 2: iterate step},
+ * the total milliseconds (host double[3]) and the number of launches (host
+ * int64[3]) since timing was enabled.
+ */
+kkm_status kkm_timing_enable(int32_t on);
+kkm_status kkm_timing_read(double *total_ms, int64_t *launches);
+
+/* Message for the last error on this thread ("" if none). */
+const char *kkm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KKM_H */

@@ -36,6 +36,8 @@ def lib():
     if _lib is None:
         path = _build.build(force=False)
         L = ctypes.CDLL(path)
+        L.oracle_threads.restype = _int
+        L.oracle_threads.argtypes = []
         L.oracle_kappa.restype = _d
         L.oracle_kappa.argtypes = [_f32p, _f32p, _i64, _int, _d, _d, _int]
         L.oracle_kernel_matrix.restype = None
@@ -58,6 +60,11 @@ def lib():
                                               _i32p, _i32, _i64p, _i64, _f64p]
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """Number of OpenMP threads the oracle's loops use."""
+    return int(lib().oracle_threads())
 
 
 def _ptr(a):

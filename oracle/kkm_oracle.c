@@ -39,11 +39,15 @@
  * and sum is rounded as written.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 enum { OR_LINEAR = 0, OR_POLY = 1, OR_GAUSS = 2 };
+
+/* Threads the OpenMP loops use (reported with the CPU timings). */
+int oracle_threads(void) { return omp_get_max_threads(); }
 enum { OR_EMPTY_INF = 0, OR_EMPTY_ZERO_CENTROID = 1 };
 
 /* kappa(x, y) from the definitions of Sec. 3.2 (and the inner product). */

@@ -1,0 +1,17 @@
+"""Kernel K-means on MI355X (gfx950): Gram matrix, SpMM row sweep, centroid
+norms and fused distance/argmin, behind the C ABI of libkkm.so.
+
+The functions below are a thin binding of that C ABI (see include/kkm.h);
+torch supplies device memory and the HIP stream.  Nothing here falls back to
+a CPU path: without the built library every call raises.
+"""
+from ._binding import (BF16, EMPTY_INF, EMPTY_ZERO_CENTROID, EXPORTS, F32, FP8_ROWSCALED, GAUSS,
+                       LINEAR, MAX_K, POLY, KKMError, alloc_kernel_matrix, gram_workspace_bytes,
+                       iterate_workspace_bytes, kkm_fit, kkm_fit_ex, kkm_gram, kkm_iterate,
+                       kkm_timing_enable, kkm_timing_read, lib)
+
+__all__ = ["kkm_gram", "kkm_iterate", "kkm_fit", "kkm_fit_ex", "kkm_timing_enable",
+           "kkm_timing_read", "alloc_kernel_matrix",
+           "gram_workspace_bytes", "iterate_workspace_bytes", "KKMError", "lib", "EXPORTS",
+           "LINEAR", "POLY", "GAUSS", "F32", "BF16", "FP8_ROWSCALED", "EMPTY_INF",
+           "EMPTY_ZERO_CENTROID", "MAX_K"]

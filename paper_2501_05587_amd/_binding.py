@@ -1,0 +1,241 @@
+"""ctypes binding of libkkm.so: argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor
+devices/dtypes/shapes, passes raw device pointers and torch's current HIP
+stream, and turns a non-zero status into an exception.  torch is imported
+first so that the library binds to the HIP runtime torch already loaded.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+LINEAR, POLY, GAUSS = 0, 1, 2
+F32, BF16, FP8_ROWSCALED = 0, 1, 2
+EMPTY_INF, EMPTY_ZERO_CENTROID = 0, 1
+MAX_K = 1024
+
+_STATUS = {0: "KKM_OK", -1: "KKM_ERR_ARG", -2: "KKM_ERR_LABEL", -3: "KKM_ERR_NOMEM",
+           -4: "KKM_ERR_HIP", -5: "KKM_ERR_UNSUPPORTED", -6: "KKM_ERR_NONFINITE"}
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkkm.so")
+
+EXPORTS = ("kkm_gram", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_workspace_bytes",
+           "kkm_fit", "kkm_fit_ex", "kkm_timing_enable", "kkm_timing_read", "kkm_last_error")
+
+
+class KKMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), message))
+        self.status = status
+
+
+_lib = None
+_vp, _i64, _i32, _d, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+
+
+def lib():
+    """Load libkkm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libkkm.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.kkm_last_error.restype = ctypes.c_char_p
+        L.kkm_last_error.argtypes = []
+        L.kkm_gram_workspace_bytes.restype = _sz
+        L.kkm_gram_workspace_bytes.argtypes = [_i64, _i64, _i32]
+        L.kkm_iterate_workspace_bytes.restype = _sz
+        L.kkm_iterate_workspace_bytes.argtypes = [_i64, _i32]
+        L.kkm_gram.restype = ctypes.c_int
+        L.kkm_gram.argtypes = [_vp, _i64, _i64, _i64, _i32, _d, _d, _i32, _i32, _i32, _vp, _i64,
+                               _vp, _vp, _sz, _vp]
+        L.kkm_iterate.restype = ctypes.c_int
+        L.kkm_iterate.argtypes = [_vp, _i32, _i64, _vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp,
+                                  _vp, _vp, _vp, _sz, _vp]
+        L.kkm_fit.restype = ctypes.c_int
+        L.kkm_fit.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _d, _d, _i32, _vp, _i32, _i32,
+                              _vp, ctypes.POINTER(_d), ctypes.POINTER(_i32), _vp, _i64, _vp]
+        L.kkm_fit_ex.restype = ctypes.c_int
+        L.kkm_fit_ex.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _d, _d, _i32, _i32, _i32, _i32,
+                                 _vp, _i32, _i32, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i32),
+                                 _vp, _i64, _vp, _vp, _vp, _vp]
+        L.kkm_timing_enable.restype = ctypes.c_int
+        L.kkm_timing_enable.argtypes = [_i32]
+        L.kkm_timing_read.restype = ctypes.c_int
+        L.kkm_timing_read.argtypes = [_vp, _vp]
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise KKMError(status, lib().kkm_last_error().decode(errors="replace"))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name, ndim=None):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("%s must be a GPU tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError("%s must have %d dims" % (name, ndim))
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _rows(t, name):
+    """(rows, cols, leading dimension) of a row-major 2-D tensor view."""
+    if t.stride(1) != 1:
+        raise ValueError("%s must have unit column stride" % name)
+    return t.shape[0], t.shape[1], t.stride(0)
+
+
+def _kstore_dtype(k_store):
+    return torch.bfloat16 if k_store == BF16 else torch.float32
+
+
+def alloc_kernel_matrix(n: int, k_store: int = F32, device="cuda") -> torch.Tensor:
+    """Uninitialised [n, n] view of a [n, ldk] buffer with ldk = n rounded up to 64."""
+    ldk = (n + 63) // 64 * 64
+    return torch.empty((n, ldk), dtype=_kstore_dtype(k_store), device=device)[:, :n]
+
+
+def gram_workspace_bytes(n: int, d: int, gram_prec: int = F32) -> int:
+    return int(lib().kkm_gram_workspace_bytes(n, d, gram_prec))
+
+
+def iterate_workspace_bytes(n: int, k: int) -> int:
+    return int(lib().kkm_iterate_workspace_bytes(n, k))
+
+
+def kkm_gram(X, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram_prec=F32, k_store=F32,
+             K=None, diagK=None, ws=None):
+    """K = kappa(X X^T) and diag(K) on the GPU.  Returns (K, diagK)."""
+    _dev(X, torch.float32, "X", 2)
+    n, d, ldx = _rows(X, "X")
+    if K is None:
+        K = alloc_kernel_matrix(n, k_store, X.device)
+    _dev(K, _kstore_dtype(k_store), "K", 2)
+    if tuple(K.shape) != (n, n):
+        raise ValueError("K must be [n, n]")
+    _, _, ldk = _rows(K, "K")
+    if diagK is None:
+        diagK = torch.empty(n, dtype=torch.float32, device=X.device)
+    _dev(diagK, torch.float32, "diagK", 1)
+    need = gram_workspace_bytes(n, d, gram_prec)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    _check(lib().kkm_gram(_ptr(X), n, d, ldx, kernel, gamma, coef0, degree, gram_prec, k_store,
+                          _ptr(K), ldk, _ptr(diagK), _ptr(ws), ws.numel(), _stream()))
+    return K, diagK
+
+
+def kkm_iterate(K, diagK, labels_in, k, empty_policy=EMPTY_INF, labels_out=None, counts_out=None,
+                n_changed=None, J_in=None, D_out=None, ctilde_out=None, ws=None, k_store=None):
+    """One reassignment step.  Returns (labels_out, counts_out, n_changed[1] int64, J_in[1] f64);
+    D_out / ctilde_out are filled when passed (True allocates them)."""
+    if k_store is None:
+        k_store = BF16 if K.dtype == torch.bfloat16 else F32
+    _dev(K, _kstore_dtype(k_store), "K", 2)
+    n, _, ldk = _rows(K, "K")
+    _dev(diagK, torch.float32, "diagK", 1)
+    _dev(labels_in, torch.int32, "labels_in", 1)
+    dev = K.device
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=dev)
+    if counts_out is None:
+        counts_out = torch.empty(k, dtype=torch.int32, device=dev)
+    if n_changed is None:
+        n_changed = torch.empty(1, dtype=torch.int64, device=dev)
+    if J_in is None:
+        J_in = torch.empty(1, dtype=torch.float64, device=dev)
+    if D_out is True:
+        D_out = torch.empty((n, k), dtype=torch.float32, device=dev)
+    if ctilde_out is True:
+        ctilde_out = torch.empty(k, dtype=torch.float32, device=dev)
+    for t, dt, nm in ((labels_out, torch.int32, "labels_out"), (counts_out, torch.int32, "counts_out"),
+                      (n_changed, torch.int64, "n_changed"), (J_in, torch.float64, "J_in")):
+        _dev(t, dt, nm)
+    if D_out is not None:
+        _dev(D_out, torch.float32, "D_out", 2)
+        if not D_out.is_contiguous() or tuple(D_out.shape) != (n, k):
+            raise ValueError("D_out must be contiguous [n, k]")
+    if ctilde_out is not None:
+        _dev(ctilde_out, torch.float32, "ctilde_out", 1)
+    need = iterate_workspace_bytes(n, k)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib().kkm_iterate(_ptr(K), k_store, ldk, _ptr(diagK), n, k, _ptr(labels_in),
+                             empty_policy, _ptr(labels_out), _ptr(counts_out), _ptr(n_changed),
+                             _ptr(J_in), _ptr(D_out), _ptr(ctilde_out), _ptr(ws), ws.numel(),
+                             _stream()))
+    return labels_out, counts_out, n_changed, J_in, D_out, ctilde_out
+
+
+def kkm_fit(X, k, labels0, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, max_iter=30,
+            check_convergence=True, K_ws=None, labels_out=None):
+    """The whole method on the GPU.  Returns (labels_out, objective, iters)."""
+    r = kkm_fit_ex(X, k, labels0, kernel, gamma, coef0, degree, max_iter=max_iter,
+                   check_convergence=check_convergence, K_ws=K_ws, labels_out=labels_out)
+    return r["labels"], r["objective"], r["iters"]
+
+
+def kkm_fit_ex(X, k, labels0, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram_prec=F32,
+               k_store=F32, empty_policy=EMPTY_INF, max_iter=30, check_convergence=True,
+               K_ws=None, labels_out=None):
+    """kkm_fit with precision forms and per-step records.  Returns a dict with
+    labels, objective, iters, J_trace, changed_trace and times_ms (Gram, steps, final J)."""
+    import numpy as np
+
+    _dev(X, torch.float32, "X", 2)
+    n, d, ldx = _rows(X, "X")
+    _dev(labels0, torch.int32, "labels0", 1)
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=X.device)
+    ldk = 0
+    if K_ws is not None:
+        _dev(K_ws, _kstore_dtype(k_store), "K_ws", 2)
+        if K_ws.shape[0] != n or K_ws.shape[1] < n:
+            raise ValueError("K_ws must have n rows and >= n columns")
+        _, _, ldk = _rows(K_ws, "K_ws")
+    J = _d()
+    it = _i32()
+    Jt = np.zeros(max_iter + 1, dtype=np.float64)
+    Ct = np.zeros(max(max_iter, 1), dtype=np.int64)
+    tm = np.zeros(3, dtype=np.float64)
+    _check(lib().kkm_fit_ex(_ptr(X), n, d, ldx, k, kernel, gamma, coef0, degree, gram_prec,
+                            k_store, empty_policy, _ptr(labels0), max_iter,
+                            int(bool(check_convergence)), _ptr(labels_out), ctypes.byref(J),
+                            ctypes.byref(it), _ptr(K_ws), ldk,
+                            Jt.ctypes.data_as(_vp), Ct.ctypes.data_as(_vp), tm.ctypes.data_as(_vp),
+                            _stream()))
+    t = int(it.value)
+    return dict(labels=labels_out, objective=J.value, iters=t, J_trace=Jt[:t + 1],
+                changed_trace=Ct[:t], times_ms=tm)
+
+
+def kkm_timing_enable(on: bool = True):
+    """Start (clearing old records) or stop event timing of Gram / sweep / step launches."""
+    _check(lib().kkm_timing_enable(int(bool(on))))
+
+
+def kkm_timing_read():
+    """{'gram'|'sweep'|'iterate': (total_ms, launches)} since timing was enabled."""
+    import numpy as np
+    ms = np.zeros(3, dtype=np.float64)
+    cnt = np.zeros(3, dtype=np.int64)
+    _check(lib().kkm_timing_read(ms.ctypes.data_as(_vp), cnt.ctypes.data_as(_vp)))
+    return {"gram": (float(ms[0]), int(cnt[0])), "sweep": (float(ms[1]), int(cnt[1])),
+            "iterate": (float(ms[2]), int(cnt[2]))}

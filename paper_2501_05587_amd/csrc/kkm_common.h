@@ -1,0 +1,103 @@
+// Internal definitions shared by the library's translation units (not part of
+// the C ABI).  Device helpers for gfx950 wave64 and the error plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kkm.h"
+
+namespace kkm {
+
+constexpr int kWave = 64;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const char *fmt, ...);
+kkm_status hip_fail(hipError_t e, const char *what);
+
+#define KKM_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return ::kkm::hip_fail(e_, #call);       \
+    } while (0)
+
+#define KKM_TRY(call)                                                  \
+    do {                                                               \
+        kkm_status s_ = (call);                                        \
+        if (s_ != KKM_OK) return s_;                                   \
+    } while (0)
+
+// ---------------------------------------------------------------- launch timing
+// When enabled (kkm_timing_enable), HIP events bracket the Gram and sweep
+// launches on their stream; kkm_timing_read turns them into totals.
+
+enum TimedKernel { TK_GRAM = 0, TK_SWEEP = 1, TK_ITERATE = 2, TK_COUNT = 3 };
+
+struct TimedSpan {
+    hipEvent_t start = nullptr, stop = nullptr;
+    int cls = -1;
+};
+TimedSpan timing_begin(int cls, hipStream_t stream);
+void timing_end(const TimedSpan &span, hipStream_t stream);
+
+// ---------------------------------------------------------------- workspace carving
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *p) : base(static_cast<char *>(p)) {}
+    template <typename T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t bytes() const { return (off + 255) & ~size_t(255); }
+};
+
+// ---------------------------------------------------------------- device helpers
+
+// Error-free transformation of a sum (Knuth's TwoSum): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum(long long v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Compensated pair (sum, error) reduction across a wave: deterministic tree.
+__device__ __forceinline__ void wave_sum2(float &s, float &c) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        float s2 = __shfl_xor(s, off, kWave);
+        float c2 = __shfl_xor(c, off, kWave);
+        float t, e;
+        two_sum(s, s2, t, e);
+        s = t;
+        c = c + c2 + e;
+    }
+}
+
+}  // namespace kkm
