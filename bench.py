@@ -30,6 +30,38 @@ METRIC = "iters/s & time-to-converge at n=200k,k=64: plain FP32 vs mixed+learned
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
 
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
+# this benchmark at n=200000 (KiB per dispatch), with the scale factors a plain
+# 1 GiB copy gave for the same counters (FETCH_SIZE read 524303 of 1048576 KiB,
+# WRITE_SIZE all of them).  Valid only while the kernel's sources hash to the
+# recorded value; otherwise the traffic is reported as null.
+TRAFFIC = {
+    "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/kkm_common.h"],
+                       "sha256": "ad7eb214be00111fbc40297312c351c754586a69032f9ad3dc9f5054c7063be3",
+                       "n": 200000, "fetch_kib": 78170184.08, "write_kib": 84946.79,
+                       "fetch_scale": 1.9999, "write_scale": 1.0},
+    "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/kkm_common.h"],
+                      "sha256": "1d2d0a36aa3a5eb89125e6a1b3eb7da4d9cc78510b961bdfa065156d686e8c8c",
+                      "n": 200000, "fetch_kib": 317951206.94, "write_kib": 188456126.5,
+                      "fetch_scale": 1.9999, "write_scale": 1.0},
+}
+
+
+def sources_sha(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, "paper_2501_05587_amd", p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel, n):
+    t = TRAFFIC[kernel]
+    if t["n"] != n or sources_sha(t["sources"]) != t["sha256"]:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -75,7 +107,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rows", type=int, default=0, help="use only the first N points (0 = all)")
     ap.add_argument("--iters", type=int, default=0, help="override the 30 fixed iterations")
-    ap.add_argument("--cpu-rows", type=int, default=8000)
+    ap.add_argument("--cpu-rows", type=int, default=24000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -143,12 +175,14 @@ def main():
     gram_launch_ms = tim["gram"][0] / max(tim["gram"][1], 1)
     gram_flops = float(n) * (n + 1) * w.d  # n(n+1)/2 dot products of length d, 2 flops each
     roof = {"bound": "hbm", "kernel": "spmm_row_sweep", "achieved": sweep_bytes / (sweep_ms * 1e-3) / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None, "avg_ms": sweep_ms,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic_bytes("spmm_row_sweep", n),
+            "algorithmic_bytes": sweep_bytes, "avg_ms": sweep_ms,
             "launches": tim["sweep"][1]}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof_g = {"bound": "mfma", "kernel": "gram_f32_mfma",
               "achieved": gram_flops / (gram_launch_ms * 1e-3) / 1e12, "peak": FP32_MFMA_PEAK_TFS,
-              "unit": "TFLOP/s", "traffic": None, "avg_ms": gram_launch_ms, "launches": tim["gram"][1]}
+              "unit": "TFLOP/s", "traffic": traffic_bytes("gram_f32_mfma", n),
+              "algorithmic_flops": gram_flops, "avg_ms": gram_launch_ms, "launches": tim["gram"][1]}
     roof_g["frac"] = roof_g["achieved"] / roof_g["peak"]
 
     conv = None
