@@ -52,7 +52,7 @@ struct Geometry {
     int64_t nchunk;
     int64_t slots;  // nchunk + k
     int64_t ldp;
-    int64_t nws;    // wave strips of columns
+    int64_t nws;    // wave strips of columns (FP32 K: the most; sizes the partial buffer)
     int64_t nstrip; // workgroup strips of columns
 };
 
@@ -222,40 +222,71 @@ __global__ __launch_bounds__(kPtsPerBlock) void v_scatter(
 
 // ---------------------------------------------------------------- 2. row sweep of K
 
-template <bool VEC>
-__device__ __forceinline__ f32x4 load_k4(const float *row, int64_t col, int64_t n) {
-    if (VEC && col + 3 < n) return *reinterpret_cast<const f32x4 *>(row + col);
-    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+// Entries of K as FP32 (4 per 16-byte load) or bfloat16 (8 per 16-byte load),
+// widened to float for the sums.
+template <typename T> struct KRow;
+template <> struct KRow<float> {
+    static constexpr int E = 4;
+    template <bool VEC>
+    static __device__ __forceinline__ void load(const float *row, int64_t col, int64_t n,
+                                                float (&v)[E]) {
+        if (VEC && col + E - 1 < n) {
+            const f32x4 w = *reinterpret_cast<const f32x4 *>(row + col);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (col + u < n) v[u] = row[col + u];
-    return v;
-}
+            for (int u = 0; u < E; ++u) v[u] = w[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < E; ++u) v[u] = (col + u < n) ? row[col + u] : 0.f;
+        }
+    }
+};
+template <> struct KRow<uint16_t> {
+    static constexpr int E = 8;
+    template <bool VEC>
+    static __device__ __forceinline__ void load(const uint16_t *row, int64_t col, int64_t n,
+                                                float (&v)[E]) {
+        if (VEC && col + E - 1 < n) {
+            const uint4 w = *reinterpret_cast<const uint4 *>(row + col);
+            const uint32_t p[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v[2 * u] = __uint_as_float(p[u] << 16);
+                v[2 * u + 1] = __uint_as_float(p[u] & 0xffff0000u);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+                v[u] = (col + u < n) ? __uint_as_float((uint32_t)row[col + u] << 16) : 0.f;
+        }
+    }
+};
 
 // Grid (column strips, chunks of L positions in V's CSR order).  Each lane owns
-// four consecutive columns; the workgroup covers 1024 columns of every row it
-// visits.  A chunk may span several clusters: the running sums are flushed to
-// the partial buffer slot (chunk + cluster) whenever the cluster changes,
-// which is unique per (chunk, cluster) pair.
-template <bool VEC>
+// E consecutive columns (one 16-byte load per row); a wave covers 64 E columns
+// and the workgroup 256 E columns of every row it visits.  A chunk may span
+// several clusters: the running sums are flushed to the partial-buffer slot
+// (chunk + cluster) whenever the cluster changes; the slot is unique per
+// (chunk, cluster) pair.
+template <typename T, bool VEC>
 __global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(
-    const float *__restrict__ K, int64_t ldk, int64_t n, int32_t k,
+    const T *__restrict__ K, int64_t ldk, int64_t n, int32_t k,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ offsets,
     const int32_t *__restrict__ labels, int64_t L, float *__restrict__ P, int64_t ldp,
     float *__restrict__ Zp, int64_t nws, const int32_t *err) {
+    constexpr int E = KRow<T>::E;
     if (*err != 0) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int64_t wave_strip = (int64_t)blockIdx.x * (kSweepThreads / kWave) + (tid >> 6);
-    const int64_t col = wave_strip * kWaveCols + (int64_t)lane * 4;
+    const int64_t col = wave_strip * (kWave * E) + (int64_t)lane * E;
     const int64_t q = blockIdx.y;
     const int64_t p_begin = q * L;
     const int64_t p_end = min(n, p_begin + L);
 
     // labels of this lane's columns (for z: the own-cluster entries)
-    int32_t own[4];
+    int32_t own[E];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) own[u] = (col + u < n) ? labels[col + u] : -1;
+    for (int u = 0; u < E; ++u) own[u] = (col + u < n) ? labels[col + u] : -1;
 
     // cluster holding position p_begin: last c with offsets[c] <= p_begin
     int32_t lo = 0, hi = k - 1;
@@ -270,52 +301,66 @@ __global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(
     while (p < p_end) {
         while (offsets[c + 1] <= p) ++c;  // skip empty clusters
         const int64_t seg_end = min(p_end, (int64_t)offsets[c + 1]);
-        f32x4 s = {0.f, 0.f, 0.f, 0.f}, e = {0.f, 0.f, 0.f, 0.f};
+        float s[E], e[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) s[u] = e[u] = 0.f;
         for (; p + 8 <= seg_end; p += 8) {
-            f32x4 v[8];
+            float v[8][E];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t j = __builtin_amdgcn_readfirstlane(perm[p + u]);
-                v[u] = load_k4<VEC>(K + j * ldk, col, n);
+            for (int r = 0; r < 8; ++r) {
+                const int64_t j = __builtin_amdgcn_readfirstlane(perm[p + r]);
+                KRow<T>::template load<VEC>(K + j * ldk, col, n, v[r]);
             }
-            const f32x4 blk = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < E; ++u) {
+                const float blk = ((v[0][u] + v[1][u]) + (v[2][u] + v[3][u])) +
+                                  ((v[4][u] + v[5][u]) + (v[6][u] + v[7][u]));
                 float t, er;
-                two_sum(s[u], blk[u], t, er);
+                two_sum(s[u], blk, t, er);
                 s[u] = t;
                 e[u] += er;
             }
         }
         if (p < seg_end) {
-            f32x4 blk = {0.f, 0.f, 0.f, 0.f};
+            float blk[E];
+#pragma unroll
+            for (int u = 0; u < E; ++u) blk[u] = 0.f;
             for (; p < seg_end; ++p) {
                 const int64_t j = __builtin_amdgcn_readfirstlane(perm[p]);
-                blk += load_k4<VEC>(K + j * ldk, col, n);
+                float v[E];
+                KRow<T>::template load<VEC>(K + j * ldk, col, n, v);
+#pragma unroll
+                for (int u = 0; u < E; ++u) blk[u] += v[u];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < E; ++u) {
                 float t, er;
                 two_sum(s[u], blk[u], t, er);
                 s[u] = t;
                 e[u] += er;
             }
         }
-        const f32x4 tot = s + e;
+        float tot[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) tot[u] = s[u] + e[u];
         const int64_t slot = q + c;
         if (col < n) {
             float *dst = P + slot * ldp + col;
-            if (col + 3 < n) {
-                *reinterpret_cast<f32x4 *>(dst) = tot;
+            if (col + E - 1 < n) {
+#pragma unroll
+                for (int u = 0; u < E; u += 4) {
+                    const f32x4 w = {tot[u], tot[u + 1], tot[u + 2], tot[u + 3]};
+                    *reinterpret_cast<f32x4 *>(dst + u) = w;
+                }
             } else {
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < E; ++u)
                     if (col + u < n) dst[u] = tot[u];
             }
         }
         float z = 0.f;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < E; ++u)
             if (own[u] == c) z += tot[u];
         z = wave_sum(z);
         if (lane == 0 && wave_strip < nws) Zp[slot * nws + wave_strip] = z;
@@ -491,10 +536,6 @@ kkm_status iterate_launch(const void *K, int32_t k_store, int64_t ldk, const flo
                           int32_t *labels_out, int32_t *counts_out, int64_t *n_changed,
                           double *J_in, float *D_out, float *ctilde_out, void *ws,
                           size_t ws_bytes, hipStream_t stream) {
-    if (k_store != KKM_F32) {
-        set_error("kkm_iterate: k_store=%d not available in this build", k_store);
-        return KKM_ERR_UNSUPPORTED;
-    }
     const Geometry g = make_geometry(n, k);
     size_t need = 0;
     IterWs w = carve(ws, g, &need);
@@ -515,21 +556,37 @@ kkm_status iterate_launch(const void *K, int32_t k_store, int64_t ldk, const flo
                        g.nblk, w.blk_hist, w.counts, w.err, w.perm, w.offsets, counts_out,
                        n_changed, w.ticket);
     KKM_HIP(hipGetLastError());
-    const float *Kf = static_cast<const float *>(K);
-    const bool vec = ((ldk % 4) == 0) && ((reinterpret_cast<uintptr_t>(K) & 15) == 0);
-    const dim3 sgrid((unsigned)g.nstrip, (unsigned)g.nchunk);
+    // one 16-byte load per lane and row: 4 FP32 or 8 BF16 columns
+    const int E = (k_store == KKM_BF16) ? 8 : 4;
+    const int64_t cols_per_wg = (int64_t)kSweepThreads * E;
+    const int64_t nstrip = (n + cols_per_wg - 1) / cols_per_wg;
+    const int64_t nws = (n + kWave * E - 1) / (kWave * E);
+    const bool vec = ((ldk % E) == 0) && ((reinterpret_cast<uintptr_t>(K) & 15) == 0);
+    const dim3 sgrid((unsigned)nstrip, (unsigned)g.nchunk);
+    const dim3 sblk(kSweepThreads);
     const TimedSpan span = timing_begin(TK_SWEEP, stream);
-    if (vec)
-        hipLaunchKernelGGL(spmm_row_sweep<true>, sgrid, dim3(kSweepThreads), 0, stream, Kf, ldk,
-                           n, k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, g.nws,
-                           w.err);
-    else
-        hipLaunchKernelGGL(spmm_row_sweep<false>, sgrid, dim3(kSweepThreads), 0, stream, Kf, ldk,
-                           n, k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, g.nws,
-                           w.err);
+    if (k_store == KKM_F32) {
+        const float *Kf = static_cast<const float *>(K);
+        if (vec)
+            hipLaunchKernelGGL((spmm_row_sweep<float, true>), sgrid, sblk, 0, stream, Kf, ldk, n,
+                               k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, nws, w.err);
+        else
+            hipLaunchKernelGGL((spmm_row_sweep<float, false>), sgrid, sblk, 0, stream, Kf, ldk, n,
+                               k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, nws, w.err);
+    } else {
+        const uint16_t *Kh = static_cast<const uint16_t *>(K);
+        if (vec)
+            hipLaunchKernelGGL((spmm_row_sweep<uint16_t, true>), sgrid, sblk, 0, stream, Kh, ldk,
+                               n, k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, nws,
+                               w.err);
+        else
+            hipLaunchKernelGGL((spmm_row_sweep<uint16_t, false>), sgrid, sblk, 0, stream, Kh, ldk,
+                               n, k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, nws,
+                               w.err);
+    }
     KKM_HIP(hipGetLastError());
     timing_end(span, stream);
-    hipLaunchKernelGGL(centroid_norms, dim3((unsigned)k), dim3(256), 0, stream, w.Zp, g.nws,
+    hipLaunchKernelGGL(centroid_norms, dim3((unsigned)k), dim3(256), 0, stream, w.Zp, nws,
                        w.offsets, g.L, k, w.ctilde, ctilde_out, w.err);
     KKM_HIP(hipGetLastError());
     hipLaunchKernelGGL(assign_fused, dim3(nblk), dim3(kPtsPerBlock),

@@ -67,14 +67,16 @@ def compare_step(K_or, k, labels_in, orc, D_gpu, labels_gpu, counts_gpu, n_chang
     return int((labels_gpu != orc["labels"]).sum())
 
 
-def gram_bound(X, kernel, gamma, coef0, degree, K_or):
+def gram_bound(X, kernel, gamma, coef0, degree, K_or, dot_rel=0.0):
     """Per-entry bound on |K_fp32 - K_exact| for an FP32 dot product of any
-    summation order, pushed through the kernel function (first order), times 4."""
+    summation order, pushed through the kernel function (first order), times 4.
+    dot_rel adds a further relative error of the dot product (a matrix unit
+    whose internal accumulation keeps fewer bits than FP32)."""
     u = 2.0 ** -24
     Xd = np.abs(X.astype(np.float64))
     d = X.shape[1]
     dot_abs = Xd @ Xd.T
-    dot_err = (d + 2) * u * dot_abs
+    dot_err = ((d + 2) * u + dot_rel) * dot_abs
     if kernel == 0:
         b = dot_err
     elif kernel == 1:
@@ -84,6 +86,6 @@ def gram_bound(X, kernel, gamma, coef0, degree, K_or):
         b = degree * np.abs(t) ** max(degree - 1, 0) * t_err + (degree + 1) * u * np.abs(K_or)
     else:
         nr = (Xd * Xd).sum(axis=1)
-        sq_err = (d + 4) * u * (nr[:, None] + nr[None, :] + 2 * dot_abs)
+        sq_err = (d + 4) * u * (nr[:, None] + nr[None, :] + 2 * dot_abs) + 2 * dot_rel * dot_abs
         b = np.abs(K_or) * (gamma * sq_err + 4 * u)
     return 4.0 * b + 1e-30
