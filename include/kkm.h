@@ -172,6 +172,86 @@ kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t
                       void *K_ws, int64_t ldk, double *J_trace, int64_t *changed_trace,
                       double *times_ms, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  The paper draws the initial labels at random (Sec.
+ * 3.4); these entry points produce a better start: a small network
+ * phi_theta: R^d -> R^h1 -> R^h2 -> R^out (GELU after the first two layers,
+ * last layer linear) is trained so that phi(x).phi(y) approximates the kernel
+ * values kappa(x, y) that kkm_gram computes, and Lloyd's iterations with
+ * explicit centroids (Sec. 2.1) on the rows of F = phi_theta(X) give labels
+ * that kkm_fit then refines exactly.
+ *
+ * Parameter vector (FP32, device, `kkm_mlp_param_count` floats, row-major):
+ *   W1 [h1, d], b1 [h1], W2 [h2, h1], b2 [h2], W3 [out, h2], b3 [out].
+ * Matrix products take bfloat16 operands (weights and activations rounded to
+ * nearest even) with FP32 accumulation; loss products and Adam are FP32.
+ * ------------------------------------------------------------------------ */
+
+int64_t kkm_mlp_param_count(int64_t d, int64_t h1, int64_t h2, int64_t out);
+
+/* F [n, ldf] = phi_theta(X [n, ldx]).  Asynchronous.  Workspace: at least
+ * kkm_mlp_forward_workspace_bytes(n, d, h1, h2, out). */
+kkm_status kkm_mlp_forward(const float *params, int64_t d, int64_t h1, int64_t h2, int64_t out,
+                           const float *X, int64_t n, int64_t ldx, float *F, int64_t ldf,
+                           void *ws, size_t ws_bytes, void *stream);
+size_t kkm_mlp_forward_workspace_bytes(int64_t n, int64_t d, int64_t h1, int64_t h2, int64_t out);
+
+/* Loss L = (1/B^2) ||Phi Phi^T - KB||_F^2 of a batch XB [B, ldx] with kernel
+ * values KB [B, ldkb] (symmetric), and dL/dparams into grad (param_count
+ * floats, device).  *loss is a device double.  Asynchronous.  Workspace: at
+ * least kkm_mlp_train_workspace_bytes(B, d, h1, h2, out). */
+kkm_status kkm_mlp_loss_grad(const float *params, int64_t d, int64_t h1, int64_t h2, int64_t out,
+                             const float *XB, int64_t B, int64_t ldx, const float *KB,
+                             int64_t ldkb, float *grad, double *loss, void *ws, size_t ws_bytes,
+                             void *stream);
+size_t kkm_mlp_train_workspace_bytes(int64_t B, int64_t d, int64_t h1, int64_t h2, int64_t out);
+
+/* One Adam step (bias-corrected, step number t >= 1) on `count` parameters:
+ * params, first and second moments adam_m / adam_v updated in place. */
+kkm_status kkm_mlp_adam(float *params, float *adam_m, float *adam_v, const float *grad,
+                        int64_t count, int32_t t, double lr, double beta1, double beta2,
+                        double eps, void *stream);
+
+/* `steps` training steps.  Step s takes the B training points listed in
+ * batch_idx[s*B .. s*B+B) (device int32, each in [0, mtrain); the caller draws
+ * them), gathers their rows of Xtrain [mtrain, ldx] and their block of the
+ * kernel matrix Ktrain [mtrain, ldk] (from kkm_gram), computes the loss and
+ * gradient and applies Adam with step numbers t0+1 .. t0+steps.  loss_trace
+ * (device double [steps]) receives each step's loss.  KKM_ERR_ARG when an
+ * index is out of range (checked before any update).  Asynchronous apart from
+ * that check. */
+kkm_status kkm_mlp_train(float *params, float *adam_m, float *adam_v, int64_t d, int64_t h1,
+                         int64_t h2, int64_t out, const float *Xtrain, int64_t mtrain,
+                         int64_t ldx, const float *Ktrain, int64_t ldk, const int32_t *batch_idx,
+                         int64_t B, int32_t steps, int32_t t0, double lr, double beta1,
+                         double beta2, double eps, double *loss_trace, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* Lloyd's iterations with explicit centroids on feature rows F [n, ldf] (f
+ * features), from labels0 (device int32 [n]), until no label changes or
+ * max_iter steps: d_ic = ||f_i - mean_{j in c} f_j||^2, lowest index on ties,
+ * empty clusters never chosen.  labels_out (device) must not alias labels0;
+ * iters (host) = steps executed; changed_trace (host int64 [max_iter],
+ * nullable) = labels changed per step.  Synchronous.  KKM_ERR_LABEL when
+ * labels0 has a label outside [0, k). */
+kkm_status kkm_feature_lloyd(const float *F, int64_t n, int64_t f, int64_t ldf, int32_t k,
+                             const int32_t *labels0, int32_t max_iter, int32_t *labels_out,
+                             int32_t *iters, int64_t *changed_trace, void *ws, size_t ws_bytes,
+                             void *stream);
+size_t kkm_feature_lloyd_workspace_bytes(int64_t n, int64_t f, int32_t k);
+
+/* K-means++ seeding (D^2 sampling, the K-means++ of Sec. 2.1) on feature rows
+ * F [n, ldf]: seed 0 is row floor(u_0 n); seed t is the first row whose running
+ * sum of squared distances to the nearest earlier seed exceeds u_t times their
+ * total (sums in FP64, fixed order).  uniforms: host double [k] in [0, 1),
+ * drawn by the caller.  seeds (device int32 [k]) receives the chosen rows and
+ * labels_out (device int32 [n]) the index of each row's nearest seed (lowest
+ * on ties).  Asynchronous. */
+kkm_status kkm_feature_kmeanspp(const float *F, int64_t n, int64_t f, int64_t ldf, int32_t k,
+                                const double *uniforms, int32_t *seeds, int32_t *labels_out,
+                                void *ws, size_t ws_bytes, void *stream);
+size_t kkm_feature_kmeanspp_workspace_bytes(int64_t n, int64_t f, int32_t k);
+
 /*
  * Launch timing for benchmarks (process-wide).  kkm_timing_enable(1) clears
  * the records and starts bracketing every Gram launch, every SpMM sweep launch

@@ -138,6 +138,34 @@ def lloyd_step(F, k, labels):
     return out, D, int((out != labels).sum())
 
 
+def kmeanspp(F, k, uniforms):
+    """K-means++ seeding by D^2 sampling (Arthur and Vassilvitskii, 2007) with the
+    caller's uniforms u_t in [0,1): seed 0 is row floor(u_0 n); seed t is the
+    first row whose running sum of dmin exceeds u_t * sum(dmin), dmin being the
+    squared distance to the nearest earlier seed.  Returns (seeds, labels of the
+    nearest seed with the lowest index on ties, margins): margins[t] is the
+    distance from u_t * total to the nearer cumulative-sum boundary, relative to
+    the total (how close the draw came to picking a neighbouring row)."""
+    F = np.asarray(F, np.float64)
+    n = F.shape[0]
+    seeds = [min(int(uniforms[0] * n), n - 1)]
+    margins = [np.inf]
+    dmin = ((F - F[seeds[0]]) ** 2).sum(axis=1)
+    for t in range(1, k):
+        cum = np.cumsum(dmin)
+        total = cum[-1]
+        target = uniforms[t] * total
+        i = int(np.searchsorted(cum, target, side="right"))
+        i = min(i, n - 1)
+        lo = cum[i - 1] if i > 0 else 0.0
+        margins.append(min(target - lo, cum[i] - target) / total if total > 0 else np.inf)
+        seeds.append(i)
+        dmin = np.minimum(dmin, ((F - F[i]) ** 2).sum(axis=1))
+    S = F[seeds]
+    D = ((F[:, None, :] - S[None, :, :]) ** 2).sum(axis=2)
+    return np.array(seeds, np.int32), np.argmin(D, axis=1).astype(np.int32), np.array(margins)
+
+
 def lloyd(F, k, labels0, max_iter):
     """Lloyd to convergence (no label changes) or max_iter steps; returns (labels, iters)."""
     cur = np.asarray(labels0, np.int32)

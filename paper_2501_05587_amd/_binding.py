@@ -23,7 +23,11 @@ _STATUS = {0: "KKM_OK", -1: "KKM_ERR_ARG", -2: "KKM_ERR_LABEL", -3: "KKM_ERR_NOM
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkkm.so")
 
 EXPORTS = ("kkm_gram", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_workspace_bytes",
-           "kkm_fit", "kkm_fit_ex", "kkm_timing_enable", "kkm_timing_read", "kkm_last_error")
+           "kkm_fit", "kkm_fit_ex", "kkm_mlp_param_count", "kkm_mlp_forward",
+           "kkm_mlp_forward_workspace_bytes", "kkm_mlp_loss_grad", "kkm_mlp_train_workspace_bytes",
+           "kkm_mlp_adam", "kkm_mlp_train", "kkm_feature_lloyd", "kkm_feature_lloyd_workspace_bytes",
+           "kkm_feature_kmeanspp", "kkm_feature_kmeanspp_workspace_bytes",
+           "kkm_timing_enable", "kkm_timing_read", "kkm_last_error")
 
 
 class KKMError(RuntimeError):
@@ -62,6 +66,32 @@ def lib():
         L.kkm_fit_ex.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _d, _d, _i32, _i32, _i32, _i32,
                                  _vp, _i32, _i32, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i32),
                                  _vp, _i64, _vp, _vp, _vp, _vp]
+        L.kkm_mlp_param_count.restype = _i64
+        L.kkm_mlp_param_count.argtypes = [_i64, _i64, _i64, _i64]
+        L.kkm_mlp_forward_workspace_bytes.restype = _sz
+        L.kkm_mlp_forward_workspace_bytes.argtypes = [_i64, _i64, _i64, _i64, _i64]
+        L.kkm_mlp_train_workspace_bytes.restype = _sz
+        L.kkm_mlp_train_workspace_bytes.argtypes = [_i64, _i64, _i64, _i64, _i64]
+        L.kkm_mlp_forward.restype = ctypes.c_int
+        L.kkm_mlp_forward.argtypes = [_vp, _i64, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _vp,
+                                      _sz, _vp]
+        L.kkm_mlp_loss_grad.restype = ctypes.c_int
+        L.kkm_mlp_loss_grad.argtypes = [_vp, _i64, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64,
+                                        _vp, _vp, _vp, _sz, _vp]
+        L.kkm_mlp_adam.restype = ctypes.c_int
+        L.kkm_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _d, _d, _d, _d, _vp]
+        L.kkm_mlp_train.restype = ctypes.c_int
+        L.kkm_mlp_train.argtypes = [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _vp, _i64, _i64, _vp,
+                                    _i64, _vp, _i64, _i32, _i32, _d, _d, _d, _d, _vp, _vp, _sz, _vp]
+        L.kkm_feature_lloyd_workspace_bytes.restype = _sz
+        L.kkm_feature_lloyd_workspace_bytes.argtypes = [_i64, _i64, _i32]
+        L.kkm_feature_lloyd.restype = ctypes.c_int
+        L.kkm_feature_lloyd.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _i32, _vp,
+                                        ctypes.POINTER(_i32), _vp, _vp, _sz, _vp]
+        L.kkm_feature_kmeanspp_workspace_bytes.restype = _sz
+        L.kkm_feature_kmeanspp_workspace_bytes.argtypes = [_i64, _i64, _i32]
+        L.kkm_feature_kmeanspp.restype = ctypes.c_int
+        L.kkm_feature_kmeanspp.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
         L.kkm_timing_enable.restype = ctypes.c_int
         L.kkm_timing_enable.argtypes = [_i32]
         L.kkm_timing_read.restype = ctypes.c_int
@@ -239,3 +269,117 @@ def kkm_timing_read():
     _check(lib().kkm_timing_read(ms.ctypes.data_as(_vp), cnt.ctypes.data_as(_vp)))
     return {"gram": (float(ms[0]), int(cnt[0])), "sweep": (float(ms[1]), int(cnt[1])),
             "iterate": (float(ms[2]), int(cnt[2]))}
+
+
+# ---------------------------------------------------------------- learned warm start
+
+MLP_DIMS = dict(h1=512, h2=512, out=256)
+
+
+def mlp_param_count(d, h1=512, h2=512, out=256) -> int:
+    return int(lib().kkm_mlp_param_count(d, h1, h2, out))
+
+
+def kkm_mlp_forward(params, X, h1=512, h2=512, out=256, F=None, ws=None):
+    """F = phi_theta(X) on the GPU (params: FP32 device vector)."""
+    _dev(params, torch.float32, "params", 1)
+    _dev(X, torch.float32, "X", 2)
+    n, d, ldx = _rows(X, "X")
+    if params.numel() != mlp_param_count(d, h1, h2, out):
+        raise ValueError("params has %d entries, expected %d" % (params.numel(),
+                                                                 mlp_param_count(d, h1, h2, out)))
+    if F is None:
+        F = torch.empty((n, out), dtype=torch.float32, device=X.device)
+    _dev(F, torch.float32, "F", 2)
+    _, _, ldf = _rows(F, "F")
+    need = int(lib().kkm_mlp_forward_workspace_bytes(n, d, h1, h2, out))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    _check(lib().kkm_mlp_forward(_ptr(params), d, h1, h2, out, _ptr(X), n, ldx, _ptr(F), ldf,
+                                 _ptr(ws), ws.numel(), _stream()))
+    return F
+
+
+def kkm_mlp_loss_grad(params, XB, KB, h1=512, h2=512, out=256, grad=None, ws=None):
+    """(grad, loss[1] float64) of (1/B^2)||Phi Phi^T - KB||^2 for one batch."""
+    _dev(params, torch.float32, "params", 1)
+    _dev(XB, torch.float32, "XB", 2)
+    _dev(KB, torch.float32, "KB", 2)
+    B, d, ldx = _rows(XB, "XB")
+    _, _, ldkb = _rows(KB, "KB")
+    if grad is None:
+        grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float64, device=XB.device)
+    need = int(lib().kkm_mlp_train_workspace_bytes(B, d, h1, h2, out))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=XB.device)
+    _check(lib().kkm_mlp_loss_grad(_ptr(params), d, h1, h2, out, _ptr(XB), B, ldx, _ptr(KB), ldkb,
+                                   _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(), _stream()))
+    return grad, loss
+
+
+def kkm_mlp_adam(params, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().kkm_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), t, lr,
+                              beta1, beta2, eps, _stream()))
+
+
+def kkm_mlp_train(params, m, v, Xtrain, Ktrain, batch_idx, t0=0, lr=1e-3, beta1=0.9,
+                  beta2=0.999, eps=1e-8, h1=512, h2=512, out=256, ws=None):
+    """Train for batch_idx.shape[0] steps (batch_idx: device int32 [steps, B]).
+    Returns the per-step losses (device float64 [steps])."""
+    _dev(Xtrain, torch.float32, "Xtrain", 2)
+    _dev(Ktrain, torch.float32, "Ktrain", 2)
+    _dev(batch_idx, torch.int32, "batch_idx", 2)
+    mt, d, ldx = _rows(Xtrain, "Xtrain")
+    _, _, ldk = _rows(Ktrain, "Ktrain")
+    steps, B = batch_idx.shape
+    if not batch_idx.is_contiguous():
+        raise ValueError("batch_idx must be contiguous")
+    losses = torch.empty(max(steps, 1), dtype=torch.float64, device=Xtrain.device)
+    need = int(lib().kkm_mlp_train_workspace_bytes(B, d, h1, h2, out))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=Xtrain.device)
+    _check(lib().kkm_mlp_train(_ptr(params), _ptr(m), _ptr(v), d, h1, h2, out, _ptr(Xtrain), mt,
+                               ldx, _ptr(Ktrain), ldk, _ptr(batch_idx), B, steps, t0, lr, beta1,
+                               beta2, eps, _ptr(losses), _ptr(ws), ws.numel(), _stream()))
+    return losses[:steps]
+
+
+def kkm_feature_lloyd(F, k, labels0, max_iter=100, labels_out=None, ws=None):
+    """Lloyd on feature rows.  Returns (labels_out, iters, changed_trace)."""
+    import numpy as np
+    _dev(F, torch.float32, "F", 2)
+    _dev(labels0, torch.int32, "labels0", 1)
+    n, f, ldf = _rows(F, "F")
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=F.device)
+    need = int(lib().kkm_feature_lloyd_workspace_bytes(n, f, k))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=F.device)
+    it = _i32()
+    tr = np.zeros(max(max_iter, 1), dtype=np.int64)
+    _check(lib().kkm_feature_lloyd(_ptr(F), n, f, ldf, k, _ptr(labels0), max_iter, _ptr(labels_out),
+                                   ctypes.byref(it), tr.ctypes.data_as(_vp), _ptr(ws), ws.numel(),
+                                   _stream()))
+    return labels_out, int(it.value), tr[:int(it.value)]
+
+
+def kkm_feature_kmeanspp(F, k, uniforms, seeds=None, labels_out=None, ws=None):
+    """K-means++ seeds on feature rows (uniforms: k host floats in [0,1)).
+    Returns (seeds, labels_out): device int32 [k] and [n]."""
+    import numpy as np
+    _dev(F, torch.float32, "F", 2)
+    n, f, ldf = _rows(F, "F")
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    if u.shape != (k,):
+        raise ValueError("need k uniforms")
+    if seeds is None:
+        seeds = torch.empty(k, dtype=torch.int32, device=F.device)
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=F.device)
+    need = int(lib().kkm_feature_kmeanspp_workspace_bytes(n, f, k))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=F.device)
+    _check(lib().kkm_feature_kmeanspp(_ptr(F), n, f, ldf, k, u.ctypes.data_as(_vp), _ptr(seeds),
+                                      _ptr(labels_out), _ptr(ws), ws.numel(), _stream()))
+    return seeds, labels_out

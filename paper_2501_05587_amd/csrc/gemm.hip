@@ -1,0 +1,162 @@
+// MFMA products for the learned feature map: 64 x 64 output tile per 256-thread
+// workgroup, 4 waves as 2 x 2, each one 32 x 32 MFMA block; k staged in LDS in
+// slabs of 32 as FP32 and rounded to the operand type when the fragments are
+// built (bfloat16: round to nearest even; FP32: unchanged).
+#include "gemm.h"
+
+namespace kkm {
+
+namespace {
+
+constexpr int TM = 64, TK = 32, TLD = TK + 1;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ __bf16 to_bf16(float f) {
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint16_t h = (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? ((u >> 16) | 0x40) : r);
+    __bf16 b;
+    __builtin_memcpy(&b, &h, 2);
+    return b;
+}
+
+__device__ __forceinline__ float gelu(float z) {
+    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// Stage a 64 x 32 operand slab (rows r0.., k k0..) into LDS as [row][k].
+template <bool KCONTIG>
+__device__ __forceinline__ void stage(const float *P, int64_t ld, int64_t rows, int64_t K,
+                                      int64_t r0, int64_t k0, float (*S)[TLD]) {
+    const int t = threadIdx.x;
+    if (KCONTIG) {
+        const int r = t >> 2, c = (t & 3) * 8;  // 8 consecutive k of one row
+        const int64_t gr = r0 + r;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int64_t gk = k0 + c + v;
+            S[r][c + v] = (gr < rows && gk < K) ? P[gr * ld + gk] : 0.f;
+        }
+    } else {
+        const int kk = t >> 3, c = (t & 7) * 8;  // 8 consecutive rows of one k
+        const int64_t gk = k0 + kk;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int64_t gr = r0 + c + v;
+            S[c + v][kk] = (gr < rows && gk < K) ? P[gk * ld + gr] : 0.f;
+        }
+    }
+}
+
+template <int OP, bool AK, bool BK>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int epi) {
+    __shared__ float As[TM][TLD], Bs[TM][TLD];
+    __shared__ double red[4];
+    const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TM;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int half = lane >> 5, l32 = lane & 31;
+
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+
+    for (int64_t k0 = 0; k0 < g.K; k0 += TK) {
+        stage<AK>(g.A, g.lda, g.M, g.K, m0, k0, As);
+        stage<BK>(g.B, g.ldb, g.N, g.K, n0, k0, Bs);
+        __syncthreads();
+        const float *ra = As[wm * 32 + l32];
+        const float *rb = Bs[wn * 32 + l32];
+        if (OP == GEMM_BF16) {
+            // lane half h supplies k = 8h .. 8h+7 of each 16-wide step (same for A and B)
+#pragma unroll
+            for (int s = 0; s < TK / 16; ++s) {
+                bf16x8 x, y;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    x[v] = to_bf16(ra[16 * s + 8 * half + v]);
+                    y[v] = to_bf16(rb[16 * s + 8 * half + v]);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc, 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < TK / 2; ++s)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[2 * s + half], rb[2 * s + half], acc,
+                                                           0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // accumulator register r of lane l: row 8*(r/4) + 4*(l/32) + r%4, column l%32
+    double sq = 0.0;
+    const int64_t n = n0 + wn * 32 + l32;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t m = m0 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        if (m >= g.M || n >= g.N) continue;
+        const float v = g.alpha * acc[r];
+        switch (epi) {
+        case EPI_STORE:
+            g.C[m * g.ldc + n] = v;
+            break;
+        case EPI_BIAS:
+            g.C[m * g.ldc + n] = v + g.bias[n];
+            break;
+        case EPI_BIAS_GELU: {
+            const float z = v + g.bias[n];
+            if (g.C) g.C[m * g.ldc + n] = z;
+            g.C2[m * g.ldc2 + n] = gelu(z);
+            break;
+        }
+        case EPI_GELU_BWD:
+            g.C[m * g.ldc + n] = v * gelu_grad(g.Zp[m * g.ldz + n]);
+            break;
+        default: {  // EPI_LOSS
+            const float e = v - g.Kb[m * g.ldkb + n];
+            g.C[m * g.ldc + n] = e;
+            sq += (double)e * (double)e;
+        }
+        }
+    }
+    if (epi == EPI_LOSS) {
+        sq = wave_sum(sq);
+        if (lane == 0) red[wave] = sq;
+        __syncthreads();
+        if (tid == 0)
+            g.part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+}  // namespace
+
+kkm_status gemm_launch(GemmOp op, bool ak, bool bk, GemmEpi epi, const GemmArgs &g,
+                       hipStream_t stream) {
+    if (g.M <= 0 || g.N <= 0) return KKM_OK;
+    const dim3 grid((unsigned)((g.N + TM - 1) / TM), (unsigned)((g.M + TM - 1) / TM));
+    const dim3 blk(256);
+    const int e = (int)epi;
+#define KKM_GEMM(OPV, AKV, BKV) \
+    hipLaunchKernelGGL((gemm_kernel<OPV, AKV, BKV>), grid, blk, 0, stream, g, e)
+    if (op == GEMM_BF16) {
+        if (ak && bk) KKM_GEMM(GEMM_BF16, true, true);
+        else if (ak && !bk) KKM_GEMM(GEMM_BF16, true, false);
+        else if (!ak && bk) KKM_GEMM(GEMM_BF16, false, true);
+        else KKM_GEMM(GEMM_BF16, false, false);
+    } else {
+        if (ak && bk) KKM_GEMM(GEMM_F32, true, true);
+        else if (ak && !bk) KKM_GEMM(GEMM_F32, true, false);
+        else if (!ak && bk) KKM_GEMM(GEMM_F32, false, true);
+        else KKM_GEMM(GEMM_F32, false, false);
+    }
+#undef KKM_GEMM
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+}  // namespace kkm

@@ -525,6 +525,29 @@ __global__ __launch_bounds__(kPtsPerBlock) void assign_fused(
 
 }  // namespace
 
+// V in CSR form from labels in [0, k): cluster sizes, row pointers (offsets)
+// and column indices (perm, stable).  blk_hist holds k * ceil(n/256) ints and
+// blk_bad ceil(n/256) ints; *err ends up non-zero when a label is out of range
+// (perm is then incomplete).  counts_out[k], *n_changed and *ticket are
+// cleared on the way, for a following assignment kernel.
+kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
+                      int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,
+                      int32_t *offsets, int32_t *counts_out, int64_t *n_changed,
+                      uint32_t *ticket, hipStream_t stream) {
+    const int64_t nblk = (n + kPtsPerBlock - 1) / kPtsPerBlock;
+    hipLaunchKernelGGL(v_block_hist, dim3((unsigned)nblk), dim3(kPtsPerBlock),
+                       (k + 1) * sizeof(int32_t), stream, labels, n, k, nblk, blk_hist, blk_bad);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(v_cluster_scan, dim3((unsigned)k), dim3(256), 0, stream, blk_hist, nblk,
+                       counts, blk_bad, err);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(v_scatter, dim3((unsigned)nblk), dim3(kPtsPerBlock),
+                       (size_t)(k + 1 + 4 * k) * sizeof(int32_t), stream, labels, n, k, nblk,
+                       blk_hist, counts, err, perm, offsets, counts_out, n_changed, ticket);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
 size_t iterate_workspace_bytes(int64_t n, int32_t k) {
     size_t bytes = 0;
     carve(nullptr, make_geometry(n, k), &bytes);
@@ -545,17 +568,8 @@ kkm_status iterate_launch(const void *K, int32_t k_store, int64_t ldk, const flo
     }
     const unsigned nblk = (unsigned)g.nblk;
     const TimedSpan whole = timing_begin(TK_ITERATE, stream);
-    hipLaunchKernelGGL(v_block_hist, dim3(nblk), dim3(kPtsPerBlock), (k + 1) * sizeof(int32_t),
-                       stream, labels_in, n, k, g.nblk, w.blk_hist, w.blk_bad);
-    KKM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(v_cluster_scan, dim3((unsigned)k), dim3(256), 0, stream, w.blk_hist,
-                       g.nblk, w.counts, w.blk_bad, w.err);
-    KKM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(v_scatter, dim3(nblk), dim3(kPtsPerBlock),
-                       (size_t)(k + 1 + 4 * k) * sizeof(int32_t), stream, labels_in, n, k,
-                       g.nblk, w.blk_hist, w.counts, w.err, w.perm, w.offsets, counts_out,
-                       n_changed, w.ticket);
-    KKM_HIP(hipGetLastError());
+    KKM_TRY(vcsr_build(labels_in, n, k, w.blk_hist, w.blk_bad, w.err, w.counts, w.perm,
+                       w.offsets, counts_out, n_changed, w.ticket, stream));
     // one 16-byte load per lane and row: 4 FP32 or 8 BF16 columns
     const int E = (k_store == KKM_BF16) ? 8 : 4;
     const int64_t cols_per_wg = (int64_t)kSweepThreads * E;

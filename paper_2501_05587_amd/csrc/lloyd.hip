@@ -1,0 +1,423 @@
+// Cheap iterations of the learned warm start: Lloyd's algorithm (the three
+// phases of the paper's Sec. 2.1) with explicit centroids on the feature rows
+// F = phi_theta(X) (n x f).  One step costs O(n f k) instead of the O(n^2) of
+// an exact step.  Per step:
+//   1. V in CSR form from the labels (shared with the exact step);
+//   2. centroid sums: chunks of CSR positions, running per-feature sums flushed
+//      at cluster boundaries (slot chunk + cluster), then a fixed-order reduce
+//      that also forms ||c_c||^2;
+//   3. G = F C^T on MFMA (FP32);
+//   4. d_ic = ||f_i||^2 - 2 G_ic + ||c_c||^2, argmin (lowest index on ties, an
+//      empty cluster at +inf), changed count.
+#include "gemm.h"
+
+namespace kkm {
+
+kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
+                      int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,
+                      int32_t *offsets, int32_t *counts_out, int64_t *n_changed,
+                      uint32_t *ticket, hipStream_t stream);
+
+namespace {
+
+constexpr int64_t kRows = 256;  // CSR positions per centroid-sum chunk
+
+struct LloydWs {
+    int32_t *blk_hist, *blk_bad, *err, *counts, *perm, *offsets, *counts_out;
+    int64_t *changed;
+    uint32_t *ticket;
+    float *fn, *Cp, *C, *cn, *G;
+    int32_t *lab[2];
+};
+
+LloydWs carve_lloyd(void *base, int64_t n, int64_t f, int32_t k, size_t *bytes) {
+    const int64_t nblk = (n + 255) / 256;
+    const int64_t slots = (n + kRows - 1) / kRows + k;
+    Carver c(base);
+    LloydWs w;
+    w.blk_hist = c.take<int32_t>((size_t)(k * nblk));
+    w.blk_bad = c.take<int32_t>((size_t)nblk);
+    w.err = c.take<int32_t>(1);
+    w.counts = c.take<int32_t>((size_t)k);
+    w.perm = c.take<int32_t>((size_t)n);
+    w.offsets = c.take<int32_t>((size_t)k + 1);
+    w.counts_out = c.take<int32_t>((size_t)k);
+    w.changed = c.take<int64_t>(1);
+    w.ticket = c.take<uint32_t>(1);
+    w.fn = c.take<float>((size_t)n);
+    w.Cp = c.take<float>((size_t)(slots * f));
+    w.C = c.take<float>((size_t)(k * f));
+    w.cn = c.take<float>((size_t)k);
+    w.G = c.take<float>((size_t)(n * k));
+    w.lab[0] = c.take<int32_t>((size_t)n);
+    w.lab[1] = c.take<int32_t>((size_t)n);
+    if (bytes) *bytes = c.bytes();
+    return w;
+}
+
+__global__ void feature_sqnorms(const float *F, int64_t n, int64_t f, int64_t ldf, float *fn) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    float s = 0.f;
+    for (int64_t t = lane; t < f; t += kWave) s = fmaf(F[row * ldf + t], F[row * ldf + t], s);
+    s = wave_sum(s);
+    if (lane == 0) fn[row] = s;
+}
+
+// grid (feature blocks of 256, chunks of kRows CSR positions)
+__global__ __launch_bounds__(256) void centroid_partials(const float *F, int64_t n, int64_t f,
+                                                         int64_t ldf, int32_t k,
+                                                         const int32_t *perm,
+                                                         const int32_t *offsets, float *Cp) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t q = blockIdx.y;
+    const int64_t p0 = q * kRows, p1 = min(n, p0 + kRows);
+    int32_t lo = 0, hi = k - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (offsets[mid] <= p0) lo = mid;
+        else hi = mid - 1;
+    }
+    int32_t c = lo;
+    int64_t p = p0;
+    while (p < p1) {
+        while (offsets[c + 1] <= p) ++c;
+        const int64_t e = min(p1, (int64_t)offsets[c + 1]);
+        float s = 0.f;
+        for (; p < e; ++p) {
+            const int64_t j = __builtin_amdgcn_readfirstlane(perm[p]);
+            if (t < f) s += F[j * ldf + t];
+        }
+        if (t < f) Cp[(q + c) * f + t] = s;
+    }
+}
+
+// one workgroup per cluster: centroid = sum of its chunk partials / |c|, and ||c||^2
+__global__ __launch_bounds__(256) void centroid_finalize(const float *Cp, int64_t f, int32_t k,
+                                                         const int32_t *offsets, float *C,
+                                                         float *cn) {
+    __shared__ float sh[256];
+    const int c = blockIdx.x;
+    const int64_t a = offsets[c], b = offsets[c + 1];
+    float sq = 0.f;
+    for (int64_t t = threadIdx.x; t < f; t += 256) {
+        float s = 0.f;
+        if (b > a) {
+            for (int64_t q = a / kRows; q <= (b - 1) / kRows; ++q) s += Cp[(q + c) * f + t];
+            s /= (float)(b - a);
+        }
+        C[(int64_t)c * f + t] = s;
+        sq = fmaf(s, s, sq);
+    }
+    sh[threadIdx.x] = sq;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cn[c] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void feature_assign(const float *G, const float *fn,
+                                                      const float *cn, const int32_t *offsets,
+                                                      int64_t n, int32_t k,
+                                                      const int32_t *labels_in,
+                                                      int32_t *labels_out, int64_t *changed) {
+    __shared__ long long wc[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    long long ch = 0;
+    if (i < n) {
+        float best = __builtin_inff();
+        int32_t arg = labels_in[i];
+        for (int32_t c = 0; c < k; ++c) {
+            if (offsets[c + 1] == offsets[c]) continue;
+            const float d = fmaf(-2.0f, G[i * k + c], fn[i]) + cn[c];
+            if (d < best) {
+                best = d;
+                arg = c;
+            }
+        }
+        labels_out[i] = arg;
+        ch = (arg != labels_in[i]);
+    }
+    ch = wave_sum(ch);
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = ch;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = wc[0] + wc[1] + wc[2] + wc[3];
+        if (t) atomicAdd((unsigned long long *)changed, (unsigned long long)t);
+    }
+}
+
+// ---------------------------------------------------------------- k-means++ seeding
+//
+// Seeding by D^2 sampling (Arthur and Vassilvitskii, 2007; the K-means++ the
+// paper's Sec. 2.1 mentions): the first seed is row floor(u_0 n); seed t+1 is
+// the first row i whose running sum of dmin exceeds u_{t+1} * sum(dmin), where
+// dmin_i is the squared distance of row i to its nearest seed so far.  The
+// uniforms u_t come from the caller.  Sums run in FP64 in a fixed order.
+
+constexpr int kKppRows = 4;  // rows per block (one wave each)
+
+__global__ __launch_bounds__(256) void kpp_update(const float *F, int64_t n, int64_t f,
+                                                  int64_t ldf, const int32_t *seeds, int t,
+                                                  float *dmin, double *bsum) {
+    __shared__ double rs[kKppRows];
+    const int64_t row = (int64_t)blockIdx.x * kKppRows + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double dm = 0.0;
+    if (row < n) {
+        const float *c = F + (int64_t)seeds[t] * ldf;
+        const float *x = F + row * ldf;
+        float s = 0.f;
+        for (int64_t u = lane; u < f; u += kWave) {
+            const float e = x[u] - c[u];
+            s = fmaf(e, e, s);
+        }
+        s = wave_sum(s);
+        const float prev = (t == 0) ? __builtin_inff() : dmin[row];
+        const float m = fminf(prev, s);
+        if (lane == 0) dmin[row] = m;
+        dm = (double)m;
+    }
+    if (lane == 0) rs[threadIdx.x >> 6] = dm;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+}
+
+// One workgroup: picks seed t+1 from the block sums and dmin.
+__global__ __launch_bounds__(1024) void kpp_select(const double *bsum, int64_t nb, const float *dmin,
+                                                   int64_t n, double u, int32_t *seeds, int t) {
+    __shared__ double part[1024];
+    __shared__ int64_t hit;
+    const int tid = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = (int64_t)tid * per, b1 = min(nb, b0 + per);
+    double s = 0.0;
+    for (int64_t b = b0; b < b1; ++b) s += bsum[b];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        double total = 0.0;
+        for (int i = 0; i < 1024; ++i) total += part[i];
+        int64_t pick = -1;
+        if (total > 0.0) {
+            const double target = u * total;
+            double run = 0.0;
+            int i = 0;
+            while (i < 1023 && run + part[i] <= target) run += part[i++];
+            int64_t b = (int64_t)i * per;
+            const int64_t bend = min(nb, b + per);
+            while (b < bend - 1 && run + bsum[b] <= target) run += bsum[b++];
+            for (int64_t r = b * kKppRows; r < min(n, (b + 1) * kKppRows); ++r) {
+                run += (double)dmin[r];
+                if (run > target) {
+                    pick = r;
+                    break;
+                }
+            }
+            if (pick < 0) pick = min(n, (b + 1) * kKppRows) - 1;  // rounding at the very end
+        } else {
+            pick = min((int64_t)(u * (double)n), n - 1);  // all rows coincide with seeds
+        }
+        hit = pick;
+    }
+    __syncthreads();
+    if (tid == 0) seeds[t + 1] = (int32_t)hit;
+}
+
+__global__ void gather_seed_rows(const float *F, int64_t ldf, int64_t f, const int32_t *seeds,
+                                 float *C) {
+    const int64_t c = blockIdx.x;
+    const int64_t src = seeds[c];
+    for (int64_t t = threadIdx.x; t < f; t += blockDim.x) C[c * f + t] = F[src * ldf + t];
+}
+
+__global__ void row_sqnorms_small(const float *C, int64_t k, int64_t f, float *cn) {
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= k) return;
+    float s = 0.f;
+    for (int64_t t = lane; t < f; t += kWave) s = fmaf(C[c * f + t], C[c * f + t], s);
+    s = wave_sum(s);
+    if (lane == 0) cn[c] = s;
+}
+
+__global__ void iota_i32(int32_t *p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = (int32_t)i;
+}
+
+__global__ void fill_one_i32(int32_t *p, int32_t v) { *p = v; }
+
+}  // namespace
+
+}  // namespace kkm
+
+using namespace kkm;
+
+extern "C" size_t kkm_feature_kmeanspp_workspace_bytes(int64_t n, int64_t f, int32_t k) {
+    if (n < 1 || f < 1 || k < 1) return 0;
+    Carver c(nullptr);
+    c.take<float>((size_t)n);                                  // dmin
+    c.take<double>((size_t)((n + kKppRows - 1) / kKppRows));   // block sums
+    c.take<float>((size_t)(k * f));                            // seed rows
+    c.take<float>((size_t)k);                                  // their norms
+    c.take<float>((size_t)n);                                  // row norms
+    c.take<float>((size_t)(n * k));                            // F S^T
+    c.take<int32_t>((size_t)k + 1);                            // offsets 0..k
+    c.take<int32_t>((size_t)n);                                // placeholder input labels
+    c.take<int64_t>(1);                                        // changed count
+    return c.bytes();
+}
+
+extern "C" kkm_status kkm_feature_kmeanspp(const float *F, int64_t n, int64_t f, int64_t ldf,
+                                           int32_t k, const double *uniforms, int32_t *seeds,
+                                           int32_t *labels_out, void *ws, size_t ws_bytes,
+                                           void *stream) {
+    if (n < 1 || f < 1 || ldf < f || k < 1 || k > n || !F || !uniforms || !seeds || !labels_out) {
+        set_error("kkm_feature_kmeanspp: bad sizes or NULL pointer");
+        return KKM_ERR_ARG;
+    }
+    for (int32_t t = 0; t < k; ++t)
+        if (!(uniforms[t] >= 0.0 && uniforms[t] < 1.0)) {
+            set_error("kkm_feature_kmeanspp: uniforms must lie in [0, 1)");
+            return KKM_ERR_ARG;
+        }
+    const size_t need = kkm_feature_kmeanspp_workspace_bytes(n, f, k);
+    if (!ws || ws_bytes < need) {
+        set_error("kkm_feature_kmeanspp: workspace of %zu bytes is smaller than %zu", ws_bytes, need);
+        return KKM_ERR_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws);
+    float *dmin = c.take<float>((size_t)n);
+    const int64_t nb = (n + kKppRows - 1) / kKppRows;
+    double *bsum = c.take<double>((size_t)nb);
+    float *C = c.take<float>((size_t)(k * f));
+    float *cn = c.take<float>((size_t)k);
+    float *fn = c.take<float>((size_t)n);
+    float *G = c.take<float>((size_t)(n * k));
+    int32_t *offs = c.take<int32_t>((size_t)k + 1);
+    int32_t *lab_in = c.take<int32_t>((size_t)n);
+    int64_t *changed = c.take<int64_t>(1);
+    const int64_t first = (int64_t)(uniforms[0] * (double)n);
+    hipLaunchKernelGGL(fill_one_i32, dim3(1), dim3(1), 0, s, seeds, (int32_t)(first < n ? first : n - 1));
+    for (int32_t t = 0; t + 1 < k; ++t) {
+        hipLaunchKernelGGL(kpp_update, dim3((unsigned)nb), dim3(256), 0, s, F, n, f, ldf, seeds, t,
+                           dmin, bsum);
+        hipLaunchKernelGGL(kpp_select, dim3(1), dim3(1024), 0, s, bsum, nb, dmin, n,
+                           uniforms[t + 1], seeds, t);
+        KKM_HIP(hipGetLastError());
+    }
+    // labels: nearest seed (lowest index on ties), via the Lloyd assignment
+    hipLaunchKernelGGL(gather_seed_rows, dim3((unsigned)k), dim3(256), 0, s, F, ldf, f, seeds, C);
+    hipLaunchKernelGGL(row_sqnorms_small, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, s, C,
+                       (int64_t)k, f, cn);
+    hipLaunchKernelGGL(feature_sqnorms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, F, n, f,
+                       ldf, fn);
+    hipLaunchKernelGGL(iota_i32, dim3((unsigned)((k + 1 + 255) / 256)), dim3(256), 0, s, offs,
+                       (int64_t)k + 1);
+    hipLaunchKernelGGL(iota_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, lab_in, n);
+    KKM_HIP(hipGetLastError());
+    GemmArgs g{};
+    g.A = F;
+    g.lda = ldf;
+    g.B = C;
+    g.ldb = f;
+    g.M = n;
+    g.N = k;
+    g.K = f;
+    g.alpha = 1.0f;
+    g.C = G;
+    g.ldc = k;
+    KKM_TRY(gemm_launch(GEMM_F32, true, true, EPI_STORE, g, s));
+    hipLaunchKernelGGL(feature_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, fn,
+                       cn, offs, n, k, lab_in, labels_out, changed);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+extern "C" size_t kkm_feature_lloyd_workspace_bytes(int64_t n, int64_t f, int32_t k) {
+    if (n < 1 || f < 1 || k < 1) return 0;
+    size_t bytes = 0;
+    carve_lloyd(nullptr, n, f, k, &bytes);
+    return bytes;
+}
+
+extern "C" kkm_status kkm_feature_lloyd(const float *F, int64_t n, int64_t f, int64_t ldf,
+                                        int32_t k, const int32_t *labels0, int32_t max_iter,
+                                        int32_t *labels_out, int32_t *iters,
+                                        int64_t *changed_trace, void *ws, size_t ws_bytes,
+                                        void *stream) {
+    if (n < 1 || f < 1 || ldf < f || k < 1 || k > n || max_iter < 0 || !F || !labels0 ||
+        !labels_out || !iters) {
+        set_error("kkm_feature_lloyd: bad sizes or NULL pointer");
+        return KKM_ERR_ARG;
+    }
+    if (k > KKM_MAX_K) {
+        set_error("kkm_feature_lloyd: k=%d exceeds KKM_MAX_K=%d", k, KKM_MAX_K);
+        return KKM_ERR_UNSUPPORTED;
+    }
+    size_t need = 0;
+    LloydWs w = carve_lloyd(ws, n, f, k, &need);
+    if (!ws || ws_bytes < need) {
+        set_error("kkm_feature_lloyd: workspace of %zu bytes is smaller than %zu", ws_bytes, need);
+        return KKM_ERR_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(feature_sqnorms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, F, n, f,
+                       ldf, w.fn);
+    KKM_HIP(hipGetLastError());
+    KKM_HIP(hipMemcpyAsync(w.lab[0], labels0, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    const int64_t nchunk = (n + kRows - 1) / kRows;
+    int cur = 0;
+    int32_t t = 0;
+    int64_t hc = -1;
+    int32_t herr = 0;
+    for (; t < max_iter; ++t) {
+        KKM_TRY(vcsr_build(w.lab[cur], n, k, w.blk_hist, w.blk_bad, w.err, w.counts, w.perm,
+                           w.offsets, w.counts_out, w.changed, w.ticket, s));
+        if (t == 0) {
+            KKM_HIP(hipMemcpyAsync(&herr, w.err, sizeof herr, hipMemcpyDeviceToHost, s));
+            KKM_HIP(hipStreamSynchronize(s));
+            if (herr) {
+                set_error("kkm_feature_lloyd: a label of labels0 lies outside [0, %d)", k);
+                return KKM_ERR_LABEL;
+            }
+        }
+        hipLaunchKernelGGL(centroid_partials, dim3((unsigned)((f + 255) / 256), (unsigned)nchunk),
+                           dim3(256), 0, s, F, n, f, ldf, k, w.perm, w.offsets, w.Cp);
+        hipLaunchKernelGGL(centroid_finalize, dim3((unsigned)k), dim3(256), 0, s, w.Cp, f, k,
+                           w.offsets, w.C, w.cn);
+        KKM_HIP(hipGetLastError());
+        GemmArgs g{};
+        g.A = F;
+        g.lda = ldf;
+        g.B = w.C;
+        g.ldb = f;
+        g.M = n;
+        g.N = k;
+        g.K = f;
+        g.alpha = 1.0f;
+        g.C = w.G;
+        g.ldc = k;
+        KKM_TRY(gemm_launch(GEMM_F32, true, true, EPI_STORE, g, s));
+        hipLaunchKernelGGL(feature_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.G,
+                           w.fn, w.cn, w.offsets, n, k, w.lab[cur], w.lab[cur ^ 1], w.changed);
+        KKM_HIP(hipGetLastError());
+        KKM_HIP(hipMemcpyAsync(&hc, w.changed, sizeof hc, hipMemcpyDeviceToHost, s));
+        KKM_HIP(hipStreamSynchronize(s));
+        if (changed_trace) changed_trace[t] = hc;
+        cur ^= 1;
+        if (hc == 0) {
+            ++t;
+            break;
+        }
+    }
+    KKM_HIP(hipMemcpyAsync(labels_out, w.lab[cur], (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    KKM_HIP(hipStreamSynchronize(s));
+    *iters = t;
+    return KKM_OK;
+}

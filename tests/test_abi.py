@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "kkm.h")
 
 def declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:kkm_status|size_t|const char \*)\s*(kkm_\w+)\(", txt, re.M)))
+    return sorted(set(re.findall(r"^(?:kkm_status|size_t|int64_t|const char \*)\s*(kkm_\w+)\(", txt, re.M)))
 
 
 @pytest.fixture(scope="module")

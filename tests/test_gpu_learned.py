@@ -1,0 +1,248 @@
+"""The learned warm start on the GPU, against the FP64 reference (oracle/mlp.py).
+
+* forward, loss and gradient of phi_theta: the oracle rounds every product
+  operand to bfloat16 at the same points as the GPU (weights and activations),
+  so the comparison measures FP32 accumulation only: gradients within 1e-3 of
+  each parameter block's norm, as fixed for this check;
+* Adam: one step, elementwise;
+* a few training steps through kkm_mlp_train against the oracle's steps;
+* feature-space Lloyd, teacher-forced per step (labels equal away from ties);
+* the gain: trained on kernel values the Gram kernel computes, the warm start
+  saves exact iterations against the plain random start and its refined labels
+  agree (ARI >= 0.99) with the oracle run converged from the same warm labels.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+D, H1, H2, OUT = 128, 512, 512, 256
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kkm():
+    import torch  # noqa: F401
+    import paper_2501_05587_amd as kkm
+    kkm.lib()
+    return kkm
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def params(seed, d=D):
+    th = omlp.init_params(d, H1, H2, OUT, seed=seed).astype(np.float64)
+    th += np.random.default_rng(seed + 1).normal(0, 0.02, th.shape)  # non-zero biases
+    return th.astype(np.float32)
+
+
+def batch(seed, B, d=D):
+    w = datagen.WORKLOADS["gmm200k"]
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0, 1, (B, d)).astype(np.float32)
+    K = oracle.kernel_matrix(X, oracle.GAUSS, 1.0 / d)
+    return X, K
+
+
+@pytest.mark.parametrize("n", [1, 63, 300])
+def test_mlp_forward_parity(kkm, n):
+    import torch
+    th = params(0)
+    X = np.random.default_rng(n).normal(0, 1, (n, D)).astype(np.float32)
+    say("mlp forward", n)
+    F = kkm.kkm_mlp_forward(to_dev(th), to_dev(X))
+    torch.cuda.synchronize()
+    ref, _ = omlp.forward(th.astype(np.float64), X, D, H1, H2, OUT, bf16_operands=True)
+    err = np.abs(F.cpu().numpy() - ref).max()
+    assert err <= 2e-4 * np.abs(ref).max() + 1e-6, err
+
+
+@pytest.mark.parametrize("B", [64, 100])
+def test_mlp_loss_grad_parity(kkm, B):
+    import torch
+    th = params(1)
+    X, K = batch(2 + B, B)
+    say("mlp grad", B)
+    g, loss = kkm.kkm_mlp_loss_grad(to_dev(th), to_dev(X), to_dev(K.astype(np.float32)))
+    torch.cuda.synchronize()
+    L_ref, g_ref = omlp.loss_and_grad(th.astype(np.float64), X, K.astype(np.float32).astype(np.float64),
+                                      D, H1, H2, OUT, bf16_operands=True)
+    assert float(loss.item()) == pytest.approx(L_ref, rel=1e-4)
+    gg = g.cpu().numpy().astype(np.float64)
+    off = 0
+    for shape in omlp.param_shapes(D, H1, H2, OUT):
+        size = int(np.prod(shape))
+        a, b = gg[off:off + size], g_ref[off:off + size]
+        assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b) + 1e-12, (shape, np.linalg.norm(a - b),
+                                                                           np.linalg.norm(b))
+        off += size
+    # and the exact (unrounded) gradient is within bfloat16's reach of it
+    _, g_exact = omlp.loss_and_grad(th.astype(np.float64), X, K, D, H1, H2, OUT)
+    assert np.linalg.norm(gg - g_exact) <= 5e-2 * np.linalg.norm(g_exact)
+
+
+def test_mlp_adam_parity(kkm):
+    import torch
+    rng = np.random.default_rng(7)
+    p = rng.normal(0, 1, 5000).astype(np.float32)
+    m = rng.normal(0, 0.1, 5000).astype(np.float32)
+    v = np.abs(rng.normal(0, 0.1, 5000)).astype(np.float32)
+    g = rng.normal(0, 1, 5000).astype(np.float32)
+    pd, md, vd = to_dev(p), to_dev(m), to_dev(v)
+    kkm.kkm_mlp_adam(pd, md, vd, to_dev(g), 3, lr=1e-2)
+    torch.cuda.synchronize()
+    pr, mr, vr = omlp.adam_step(p.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                                g.astype(np.float64), 3, lr=1e-2)
+    np.testing.assert_allclose(pd.cpu().numpy(), pr, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(md.cpu().numpy(), mr, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(vd.cpu().numpy(), vr, rtol=1e-6, atol=1e-8)
+
+
+def test_mlp_train_steps_match_oracle(kkm):
+    import torch
+    m_train, B, steps = 300, 64, 3
+    rng = np.random.default_rng(11)
+    Xt = rng.normal(0, 1, (m_train, D)).astype(np.float32)
+    Kt = oracle.kernel_matrix(Xt, oracle.GAUSS, 1.0 / D).astype(np.float32)
+    idx = np.stack([rng.choice(m_train, B, replace=False) for _ in range(steps)]).astype(np.int32)
+    th = params(3)
+    pd = to_dev(th)
+    md = torch.zeros_like(pd)
+    vd = torch.zeros_like(pd)
+    say("mlp train steps")
+    losses = kkm.kkm_mlp_train(pd, md, vd, to_dev(Xt), to_dev(Kt), to_dev(idx), lr=1e-3)
+    torch.cuda.synchronize()
+    t = th.astype(np.float64)
+    mo = np.zeros_like(t)
+    vo = np.zeros_like(t)
+    for s in range(steps):
+        ib = idx[s]
+        L, g = omlp.loss_and_grad(t, Xt[ib], Kt[np.ix_(ib, ib)].astype(np.float64), D, H1, H2, OUT,
+                                  bf16_operands=True)
+        assert float(losses[s].item()) == pytest.approx(L, rel=2e-3)
+        t, mo, vo = omlp.adam_step(t, mo, vo, g, s + 1, lr=1e-3)
+    # each coordinate moved by about lr per step; the two runs stay within a small part of that
+    moved = np.abs(t - th)
+    diff = np.abs(pd.cpu().numpy() - t)
+    assert np.median(diff) <= 0.05 * np.median(moved)
+    assert diff.max() <= 2.5 * 1e-3  # at most a couple of steps' worth anywhere (sign flips of tiny grads)
+
+
+@pytest.mark.parametrize("n,f,k", [(3000, 256, 17), (700, 40, 5), (65, 3, 64)])
+def test_feature_lloyd_teacher_forced(kkm, n, f, k):
+    import torch
+    rng = np.random.default_rng(n + f)
+    mu = rng.normal(0, 2, (k, f))
+    F = (mu[rng.integers(0, k, n)] + rng.normal(0, 1, (n, f))).astype(np.float32)
+    cur = rng.integers(0, k, n).astype(np.int32)
+    Fd = to_dev(F)
+    for t in range(6):
+        ref, Dr, ch = omlp.lloyd_step(F, k, cur)
+        say("feature lloyd", n, f, k, "step", t)
+        lab, it, tr = kkm.kkm_feature_lloyd(Fd, k, to_dev(cur), max_iter=1)
+        torch.cuda.synchronize()
+        lab = lab.cpu().numpy()
+        srt = np.sort(np.where(np.isfinite(Dr), Dr, np.inf), axis=1)
+        gap = srt[:, 1] - srt[:, 0] if k > 1 else np.full(n, np.inf)
+        scale = (F.astype(np.float64) ** 2).sum(axis=1) + np.nanmax(np.where(np.isfinite(Dr), Dr, 0), axis=1)
+        near = gap < 1e-5 * scale
+        assert it == 1 and tr[0] == int((lab != cur).sum())
+        assert not ((lab != ref) & ~near).any()
+        if ch == 0:
+            break
+        cur = ref
+
+
+def test_feature_lloyd_converges_and_rejects_bad_labels(kkm):
+    import torch
+    rng = np.random.default_rng(5)
+    F = rng.normal(0, 1, (500, 8)).astype(np.float32)
+    l0 = rng.integers(0, 6, 500).astype(np.int32)
+    lab, it, tr = kkm.kkm_feature_lloyd(to_dev(F), 6, to_dev(l0), max_iter=200)
+    torch.cuda.synchronize()
+    ref, it_ref = omlp.lloyd(F, 6, l0, 200)
+    assert tr[-1] == 0
+    assert oracle.adjusted_rand_index(lab.cpu().numpy(), ref) >= 0.99
+    bad = l0.copy()
+    bad[3] = 9
+    with pytest.raises(kkm.KKMError):
+        kkm.kkm_feature_lloyd(to_dev(F), 6, to_dev(bad), max_iter=3)
+
+
+@pytest.mark.parametrize("n,f,k", [(2000, 256, 16), (333, 7, 9), (40, 3, 40)])
+def test_feature_kmeanspp_parity(kkm, n, f, k):
+    import torch
+    rng = np.random.default_rng(n + k)
+    mu = rng.normal(0, 3, (k, f))
+    F = (mu[rng.integers(0, k, n)] + rng.normal(0, 1, (n, f))).astype(np.float32)
+    u = rng.random(k)
+    say("kmeans++", n, f, k)
+    seeds, lab = kkm.kkm_feature_kmeanspp(to_dev(F), k, u)
+    torch.cuda.synchronize()
+    s_ref, lab_ref, margins = omlp.kmeanspp(F, k, u)
+    s_gpu = seeds.cpu().numpy()
+    diff = np.nonzero(s_gpu != s_ref)[0]
+    if diff.size:
+        # FP32 distances on the GPU may only move a draw that landed next to a boundary
+        assert margins[diff[0]] < 1e-5, (diff[0], margins[diff[0]])
+    else:
+        D = ((F.astype(np.float64)[:, None] - F.astype(np.float64)[s_ref][None]) ** 2).sum(-1)
+        srt = np.sort(D, axis=1)
+        near = (srt[:, 1] - srt[:, 0]) < 1e-5 * srt[:, 1] if k > 1 else np.zeros(n, bool)
+        assert not ((lab.cpu().numpy() != lab_ref) & ~near).any()
+
+
+def test_learned_warm_start_gain(kkm):
+    """Train phi on the 32-component mixture in R^128 (Gaussian 1/128) with
+    kernel values from kkm_gram, then cluster fresh draws: k-means++ seeds and
+    Lloyd in phi-space, exact refinement, against the plain random start."""
+    import torch
+    d, k, sigma, gamma = 128, 32, 0.5, 1.0 / 128
+    means = datagen.gmm_means(d, k, 5000)
+    Xtr, _ = datagen.gmm(2048, d, k, sigma, 5001, means=means)
+    Xte, truth = datagen.gmm(6000, d, k, sigma, 5002, means=means)
+    l0 = datagen.uniform_labels(6000, k, 5003)
+    say("learned: gram of the training points")
+    Xtr_d = to_dev(Xtr)
+    Ktr, _ = kkm.kkm_gram(Xtr_d, kkm.GAUSS, gamma)
+    Ktr = Ktr.contiguous()
+    rng = np.random.default_rng(5004)
+    steps, B = 400, 256
+    idx = np.stack([rng.choice(2048, B, replace=False) for _ in range(steps)]).astype(np.int32)
+    pd = to_dev(omlp.init_params(d, H1, H2, OUT, seed=5005))
+    md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
+    say("learned: training")
+    losses = kkm.kkm_mlp_train(pd, md, vd, Xtr_d, Ktr, to_dev(idx), lr=1e-3).cpu().numpy()
+    say("learned: loss %.4g -> %.4g" % (losses[:10].mean(), losses[-10:].mean()))
+    assert losses[-10:].mean() < 0.2 * losses[:10].mean()
+    Xd = to_dev(Xte)
+    F = kkm.kkm_mlp_forward(pd, Xd)
+    _, seeded = kkm.kkm_feature_kmeanspp(F, k, np.random.default_rng(5006).random(k))
+    warm, cheap_iters, _ = kkm.kkm_feature_lloyd(F, k, seeded, max_iter=100)
+    plain = kkm.kkm_fit_ex(Xd, k, to_dev(l0), kkm.GAUSS, gamma, max_iter=200)
+    learned = kkm.kkm_fit_ex(Xd, k, warm, kkm.GAUSS, gamma, max_iter=200)
+    torch.cuda.synchronize()
+    K_or = oracle.kernel_matrix(Xte, oracle.GAUSS, gamma)
+    ref = oracle.fit(K_or, k, warm.cpu().numpy(), 200)
+    ari_oracle = oracle.adjusted_rand_index(learned["labels"].cpu().numpy(), ref["labels"])
+    say("learned: cheap %d, exact %d (plain %d); J %.6g vs plain %.6g; ARI vs oracle-from-warm %.4f; "
+        "ARI vs truth %.4f vs plain %.4f" % (
+            cheap_iters, learned["iters"], plain["iters"], learned["objective"], plain["objective"],
+            ari_oracle, oracle.adjusted_rand_index(learned["labels"].cpu().numpy(), truth),
+            oracle.adjusted_rand_index(plain["labels"].cpu().numpy(), truth)))
+    assert ari_oracle >= 0.99
+    assert learned["iters"] < plain["iters"]
+    assert learned["objective"] <= plain["objective"] * (1 + 1e-6)

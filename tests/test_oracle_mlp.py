@@ -97,6 +97,35 @@ def test_adam_first_step():
     np.testing.assert_allclose(v, 0.001 * g * g)
 
 
+def test_kmeanspp_samples_proportional_to_d2():
+    # second seed after a fixed first one: frequencies follow dmin / sum(dmin)
+    rng = np.random.default_rng(8)
+    F = rng.normal(0, 1, (12, 3))
+    p = ((F - F[0]) ** 2).sum(axis=1)
+    p = p / p.sum()
+    draws = 20000
+    counts = np.zeros(12)
+    u = rng.random((draws, 2))
+    u[:, 0] = 0.0  # first seed = row 0
+    for t in range(draws):
+        seeds, _, _ = mlp.kmeanspp(F, 2, u[t])
+        counts[seeds[1]] += 1
+    assert counts[0] == 0
+    chi2 = ((counts[1:] - draws * p[1:]) ** 2 / (draws * p[1:])).sum()
+    assert chi2 < 40.0  # 10 degrees of freedom; p-value ~ 1e-5 at 40
+
+
+def test_kmeanspp_separated_blobs_and_labels():
+    rng = np.random.default_rng(9)
+    mu = np.array([[0.0, 0.0], [100.0, 0.0], [0.0, 100.0]])
+    F = mu[np.repeat(np.arange(3), 50)] + rng.normal(0, 1, (150, 2))
+    seeds, lab, margins = mlp.kmeanspp(F, 3, rng.random(3))
+    assert len({int(s) // 50 for s in seeds}) == 3  # one seed per blob
+    D = ((F[:, None] - F[seeds][None]) ** 2).sum(-1)
+    np.testing.assert_array_equal(lab, np.argmin(D, axis=1))
+    assert np.all(margins[1:] >= 0)
+
+
 def test_feature_lloyd_matches_sklearn():
     sk = pytest.importorskip("sklearn.cluster")
     rng = np.random.default_rng(6)
