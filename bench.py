@@ -1,21 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark: Kernel K-means on one MI355X, n=200000, d=1024, k=64.
 
-One step = one complete run of the method on the resident input: the Gram
-kernel K = kappa(X X^T) (Gaussian, gamma = 1/1024, FP32 MFMA, K stored FP32,
-160 GB) followed by 30 reassignment steps (V in CSR form, SpMM row sweep of K,
-centroid norms, fused distance/argmin/histogram) and the FP64 objective of the
-final labels: the paper's protocol of exactly 30 iterations.
+Workload: a 64-component Gaussian mixture in R^1024 (means N(0,1), sigma 0.5),
+Gaussian kernel gamma = 1/1024, random initial labels.
 
-Printed (one JSON line): whole-job iterations per second over the timed steps
-(Gram included), the Gram and per-iteration times, time-to-converge from the
-same random labels with the convergence test on, the roofline position of the
-dominant kernel (the SpMM sweep, HBM-bound) and of the Gram (MFMA-bound), both
-from HIP-event timings of those launches inside the timed region, and the FP64
-oracle timed on the host on a bounded prefix of the same workload.
+Plain FP32 leg (the timed steps behind `value`).  One step = one complete run
+of the method on the resident input: the Gram kernel K = kappa(X X^T) (FP32
+MFMA, K stored FP32, 160 GB) followed by 30 reassignment steps (V in CSR form,
+SpMM row sweep of K, centroid norms, fused distance/argmin/histogram) and the
+FP64 objective of the final labels: the paper's protocol of exactly 30
+iterations.  `value` = iterations executed / timed wall time, Gram included.
+
+Also reported:
+* time-to-converge of the plain FP32 form from the random labels;
+* the mixed + learned form: BF16 Gram with K stored BF16 (80 GB), a feature
+  network trained beforehand on 10^7 kernel-value pairs of the same mixture
+  (training time reported separately), k-means++ and Lloyd in feature space,
+  then exact refinement to convergence; its time-to-converge and the ARI of its
+  labels against the plain FP32 form converged from the same warm labels;
+* roofline positions of the sweep (HBM) and the Gram (MFMA) from HIP-event
+  timings of those launches, and HBM traffic from the recorded counters;
+* the FP64 oracle timed on the host on a bounded prefix of the workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows N]
-       [--no-cpu-baseline] [--copy-calibration]
+       [--no-cpu-baseline] [--no-converge] [--no-learned] [--copy-calibration]
 """
 import argparse
 import json
@@ -29,6 +37,7 @@ sys.path.insert(0, ROOT)
 METRIC = "iters/s & time-to-converge at n=200k,k=64: plain FP32 vs mixed+learned @ARI≥.99"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
+BF16_MFMA_PEAK_TFS = 2500.0
 
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
 # this benchmark at n=200000 (KiB per dispatch), with the scale factors a plain
@@ -45,6 +54,11 @@ TRAFFIC = {
                       "n": 200000, "fetch_kib": 317951206.94, "write_kib": 188456126.5,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }
+
+# feature network and its training (learned warm start)
+H1, H2, OUT = 512, 512, 256
+TRAIN_BATCH, TRAIN_STEPS, TRAIN_LR = 64, 2442, 1e-3  # 2442 * 64^2 = 1.0e7 kernel values
+WARM_RESTARTS, WARM_MAX_ITER = 4, 60
 
 
 def sources_sha(paths):
@@ -79,6 +93,26 @@ def copy_calibration():
     log("copy calibration: 5 copies of %d bytes" % (4 * n))
 
 
+def ari(a, b):
+    """Adjusted Rand index (Hubert and Arabie) of two labellings, host numpy."""
+    import numpy as np
+    a = np.asarray(a)
+    b = np.asarray(b)
+    n = a.size
+    _, ai = np.unique(a, return_inverse=True)
+    _, bi = np.unique(b, return_inverse=True)
+    t = np.zeros((ai.max() + 1, bi.max() + 1), np.int64)
+    np.add.at(t, (ai, bi), 1)
+
+    def comb(x):
+        return float((x.astype(np.float64) * (x - 1) / 2).sum())
+
+    sij, sa, sb = comb(t), comb(t.sum(1)), comb(t.sum(0))
+    exp = sa * sb / (n * (n - 1) / 2)
+    mx = 0.5 * (sa + sb)
+    return 1.0 if mx == exp else (sij - exp) / (mx - exp)
+
+
 def cpu_baseline(w, rows, iters):
     """The FP64 oracle on the first `rows` points: K from the definition and
     `iters` fixed steps; time scaled to the full n by (n/rows)^2 (both parts
@@ -100,6 +134,48 @@ def cpu_baseline(w, rows, iters):
                           rows, w.n, iters, t1 - t0, t2 - t1, rows, scale)}
 
 
+def train_feature_map(kkm, torch, w, dev):
+    """Train phi_theta on 10^7 kernel values of fresh draws of the same mixture:
+    TRAIN_STEPS batches of TRAIN_BATCH new points, each batch's kernel values
+    computed by the Gram kernel.  Returns (params, report)."""
+    import datagen
+    m = TRAIN_STEPS * TRAIN_BATCH
+    means = datagen.gmm_means(w.d, w.k, w.data_seed)
+    Xtr, _ = datagen.gmm(m, w.d, w.k, 0.5, w.data_seed + 30000, means=means)
+    params = torch.from_numpy(datagen.mlp_init_params(w.d, H1, H2, OUT, w.data_seed + 30002)).to(dev)
+    mo, vo = torch.zeros_like(params), torch.zeros_like(params)
+    Xd = torch.from_numpy(Xtr).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = kkm.kkm_mlp_train_fresh(params, mo, vo, Xd, TRAIN_BATCH, w.kernel, w.gamma, lr=TRAIN_LR)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    lh = losses.cpu().numpy()
+    rep = {"train_points": m, "kernel_values": TRAIN_STEPS * TRAIN_BATCH ** 2, "batch": TRAIN_BATCH,
+           "steps": TRAIN_STEPS, "seconds": secs, "loss_first10": float(lh[:10].mean()),
+           "loss_last10": float(lh[-10:].mean()), "params": int(params.numel()),
+           "net": "%d-%d-%d-%d GELU" % (w.d, H1, H2, OUT)}
+    log("feature map trained in %.2f s: loss %.4g -> %.4g" % (secs, rep["loss_first10"], rep["loss_last10"]))
+    return params, rep
+
+
+def warm_labels(kkm, w, params, Xd, seed):
+    """phi_theta(X), then WARM_RESTARTS k-means++ seedings each followed by
+    Lloyd in feature space; keeps the labelling with the lowest feature-space
+    objective.  Returns (labels, cheap iterations summed over restarts)."""
+    import datagen
+    F = kkm.kkm_mlp_forward(params, Xd, H1, H2, OUT)
+    best, cheap = None, 0
+    for r in range(WARM_RESTARTS):
+        _, seeded = kkm.kkm_feature_kmeanspp(F, w.k, datagen.uniforms(w.k, seed + r))
+        lab, it, _, obj = kkm.kkm_feature_lloyd(F, w.k, seeded, max_iter=WARM_MAX_ITER,
+                                                return_objective=True)
+        cheap += it
+        if best is None or obj < best[0]:
+            best = (obj, lab)
+    return best[1], cheap
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +186,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=24000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
@@ -145,6 +222,7 @@ def main():
     del X
     torch.cuda.synchronize()
 
+    # ------------------------------------------------------------ plain FP32, fixed 30 iterations
     def step():
         return kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, w.coef0, w.degree,
                               max_iter=iters, check_convergence=False, K_ws=K, labels_out=lab)
@@ -176,8 +254,7 @@ def main():
     gram_flops = float(n) * (n + 1) * w.d  # n(n+1)/2 dot products of length d, 2 flops each
     roof = {"bound": "hbm", "kernel": "spmm_row_sweep", "achieved": sweep_bytes / (sweep_ms * 1e-3) / 1e9,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": traffic_bytes("spmm_row_sweep", n),
-            "algorithmic_bytes": sweep_bytes, "avg_ms": sweep_ms,
-            "launches": tim["sweep"][1]}
+            "algorithmic_bytes": sweep_bytes, "avg_ms": sweep_ms, "launches": tim["sweep"][1]}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof_g = {"bound": "mfma", "kernel": "gram_f32_mfma",
               "achieved": gram_flops / (gram_launch_ms * 1e-3) / 1e12, "peak": FP32_MFMA_PEAK_TFS,
@@ -185,19 +262,88 @@ def main():
               "algorithmic_flops": gram_flops, "avg_ms": gram_launch_ms, "launches": tim["gram"][1]}
     roof_g["frac"] = roof_g["achieved"] / roof_g["peak"]
 
-    conv = None
+    # ------------------------------------------------------------ plain FP32 to convergence
+    plain = None
     if not args.no_converge:
         torch.cuda.synchronize()
         tc = time.perf_counter()
         rc = kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, w.coef0, w.degree, max_iter=300,
                             check_convergence=True, K_ws=K, labels_out=lab)
         torch.cuda.synchronize()
-        conv = {"seconds": time.perf_counter() - tc, "iters": rc["iters"],
-                "objective": rc["objective"], "gram_ms": rc["times_ms"][0]}
-        import oracle as _o  # ARI by its definition (test infrastructure, reporting only)
-        conv["ari_vs_truth"] = _o.adjusted_rand_index(lab.cpu().numpy(), truth)
-        conv["empty_clusters"] = int((np.bincount(lab.cpu().numpy(), minlength=w.k) == 0).sum())
-        log("converged: %d iterations in %.3f s" % (rc["iters"], conv["seconds"]))
+        labs = lab.cpu().numpy()
+        plain = {"seconds": time.perf_counter() - tc, "iters": rc["iters"], "objective": rc["objective"],
+                 "gram_ms": rc["times_ms"][0], "iter_ms": rc["times_ms"][1] / max(rc["iters"], 1),
+                 "ari_vs_truth": ari(labs, truth),
+                 "empty_clusters": int((np.bincount(labs, minlength=w.k) == 0).sum())}
+        log("plain converged: %d iterations in %.3f s, J=%.6f" % (rc["iters"], plain["seconds"],
+                                                                  rc["objective"]))
+
+    # ------------------------------------------------------------ mixed + learned
+    learned = None
+    if not args.no_learned and not args.no_converge:
+        params, train_rep = train_feature_map(kkm, torch, w, dev)
+        useed = w.label_seed + 30003
+        # reference: the plain FP32 form converged from the same warm labels
+        warm, cheap = warm_labels(kkm, w, params, Xd, useed)
+        ref = kkm.kkm_fit_ex(Xd, w.k, warm, w.kernel, w.gamma, max_iter=300, check_convergence=True,
+                             K_ws=K, labels_out=lab)
+        ref_labels = lab.cpu().numpy()
+        log("reference from warm labels: %d iterations, J=%.6f" % (ref["iters"], ref["objective"]))
+        del K
+        torch.cuda.empty_cache()
+        K16 = kkm.alloc_kernel_matrix(n, kkm.BF16, dev)
+        lab16 = torch.empty(n, dtype=torch.int32, device=dev)
+
+        def mixed_learned():
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            wl, ch = warm_labels(kkm, w, params, Xd, useed)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            r = kkm.kkm_fit_ex(Xd, w.k, wl, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
+                               max_iter=300, check_convergence=True, K_ws=K16, labels_out=lab16)
+            torch.cuda.synchronize()
+            return time.perf_counter() - ta, tb - ta, ch, r
+
+        mixed_learned()  # warm-up of the whole leg
+        runs = [mixed_learned() for _ in range(3)]
+        secs = float(np.median([x[0] for x in runs]))
+        _, _, ch, r = runs[-1]
+        ml_labels = lab16.cpu().numpy()
+        # per-iteration rate of the mixed form: 30 fixed iterations on the BF16 K
+        kkm.kkm_timing_enable(True)
+        rf = kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
+                            max_iter=iters, check_convergence=False, K_ws=K16, labels_out=lab16)
+        torch.cuda.synchronize()
+        tim16 = kkm.kkm_timing_read()
+        kkm.kkm_timing_enable(False)
+        sw16 = tim16["sweep"][0] / max(tim16["sweep"][1], 1)
+        g16 = tim16["gram"][0] / max(tim16["gram"][1], 1)
+        learned = {
+            "seconds": secs, "warm_start_seconds": float(np.median([x[1] for x in runs])),
+            "cheap_iters": ch, "exact_iters": r["iters"], "objective": r["objective"],
+            "gram": "bf16 mfma", "k_store": "bf16", "gram_ms": r["times_ms"][0],
+            "iter_ms": rf["times_ms"][1] / max(rf["iters"], 1),
+            "iters_per_s": rf["iters"] / (rf["times_ms"][1] * 1e-3),
+            "ari_vs_fp32_from_same_warm_start": ari(ml_labels, ref_labels),
+            "ari_vs_truth": ari(ml_labels, truth),
+            "empty_clusters": int((np.bincount(ml_labels, minlength=w.k) == 0).sum()),
+            "fp32_from_warm_start": {"iters": ref["iters"], "objective": ref["objective"]},
+            "sweep_bf16": {"avg_ms": sw16, "achieved_gbs": float(n) * n * 2 / (sw16 * 1e-3) / 1e9,
+                           "frac_hbm": float(n) * n * 2 / (sw16 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "gram_bf16": {"avg_ms": g16, "achieved_tflops": gram_flops / (g16 * 1e-3) / 1e12,
+                          "frac_mfma": gram_flops / (g16 * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFS},
+            "training": train_rep,
+        }
+        if plain:
+            learned["speedup_time_to_converge_vs_plain"] = plain["seconds"] / secs
+        log("mixed+learned: %.3f s (warm start %.3f s, %d cheap + %d exact iterations), ARI vs FP32 "
+            "from same start %.4f" % (secs, learned["warm_start_seconds"], ch, r["iters"],
+                                       learned["ari_vs_fp32_from_same_warm_start"]))
+        del K16
+    else:
+        del K
+    torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
@@ -218,13 +364,12 @@ def main():
                    "parallelism": "single gpu"},
         "gram_ms": gram_ms,
         "iter_ms": iter_ms,
-        "time_to_converge": conv,
+        "plain_fp32_to_convergence": plain,
+        "mixed_learned_to_convergence": learned,
         "roofline": roof,
         "roofline_gram": roof_g,
         "cpu_baseline": None,
     }
-    del K
-    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_rows, n), iters)
     print(json.dumps(out), flush=True)

@@ -183,3 +183,36 @@ def batched_instances(count: int = 512, seed_base: int = 4000):
         out.append(dict(n=n, d=d, k=k, sigma=0.3, gamma=1.0 / d, seed=seed_base + b,
                         label_seed=seed_base + b + 100000))
     return out
+
+
+def mlp_init_params(d: int, h1: int = 512, h2: int = 512, out: int = 256, seed: int = 0):
+    """Initial parameters of the feature network, flat float32 in the order
+    W1 [h1, d], b1 [h1], W2 [h2, h1], b2 [h2], W3 [out, h2], b3 [out]:
+    W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)), b = 0."""
+    rng = np.random.default_rng([int(seed), 0x6D6C70])  # tag "mlp"
+    parts = []
+    for rows, cols in ((h1, d), (h2, h1), (out, h2)):
+        lim = 1.0 / math.sqrt(cols)
+        parts.append(rng.uniform(-lim, lim, rows * cols))
+        parts.append(np.zeros(rows))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def training_pairs_rows(pairs: float = 1e7) -> int:
+    """Smallest m with m (m - 1) / 2 >= pairs: the training points whose
+    distinct pairs carry that many kernel values."""
+    m = int(math.ceil((1 + math.sqrt(1 + 8 * pairs)) / 2))
+    while m * (m - 1) // 2 < pairs:
+        m += 1
+    return m
+
+
+def batch_indices(m: int, batch: int, steps: int, seed: int):
+    """Training batches: `steps` rows of `batch` distinct indices in [0, m), int32."""
+    rng = np.random.default_rng([int(seed), 0x62617463])  # tag "batc"
+    return np.stack([rng.choice(m, batch, replace=False) for _ in range(steps)]).astype(np.int32)
+
+
+def uniforms(count: int, seed: int):
+    """Uniform draws in [0, 1) (k-means++ seeding), float64."""
+    return np.random.default_rng([int(seed), 0x756E6966]).random(count)  # tag "unif"

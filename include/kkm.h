@@ -227,17 +227,35 @@ kkm_status kkm_mlp_train(float *params, float *adam_m, float *adam_v, int64_t d,
                          double beta2, double eps, double *loss_trace, void *ws, size_t ws_bytes,
                          void *stream);
 
+/* `steps` training steps on fresh batches: step s takes rows s*B .. s*B+B-1 of
+ * Xtrain [steps*B, ldx], computes their B x B kernel values with the Gram
+ * kernel (FP32; kernel_type/gamma/coef0/degree as kkm_gram), then the loss,
+ * the gradient and an Adam step (step numbers t0+1 .. t0+steps).  Over all
+ * steps the network sees steps * B(B-1)/2 distinct kernel-value pairs.
+ * loss_trace: device double [steps].  Asynchronous.  Workspace: at least
+ * kkm_mlp_train_fresh_workspace_bytes(B, d, h1, h2, out). */
+kkm_status kkm_mlp_train_fresh(float *params, float *adam_m, float *adam_v, int64_t d, int64_t h1,
+                               int64_t h2, int64_t out, const float *Xtrain, int64_t ldx,
+                               int64_t B, int32_t steps, int32_t t0, int32_t kernel_type,
+                               double gamma, double coef0, int32_t degree, double lr,
+                               double beta1, double beta2, double eps, double *loss_trace,
+                               void *ws, size_t ws_bytes, void *stream);
+size_t kkm_mlp_train_fresh_workspace_bytes(int64_t B, int64_t d, int64_t h1, int64_t h2,
+                                           int64_t out);
+
 /* Lloyd's iterations with explicit centroids on feature rows F [n, ldf] (f
  * features), from labels0 (device int32 [n]), until no label changes or
  * max_iter steps: d_ic = ||f_i - mean_{j in c} f_j||^2, lowest index on ties,
  * empty clusters never chosen.  labels_out (device) must not alias labels0;
  * iters (host) = steps executed; changed_trace (host int64 [max_iter],
- * nullable) = labels changed per step.  Synchronous.  KKM_ERR_LABEL when
- * labels0 has a label outside [0, k). */
+ * nullable) = labels changed per step; objective (host double, nullable) =
+ * sum_i min_c d_ic of the last step, i.e. the feature-space objective of
+ * labels_out when that step changed nothing (NaN if no step ran).
+ * Synchronous.  KKM_ERR_LABEL when labels0 has a label outside [0, k). */
 kkm_status kkm_feature_lloyd(const float *F, int64_t n, int64_t f, int64_t ldf, int32_t k,
                              const int32_t *labels0, int32_t max_iter, int32_t *labels_out,
-                             int32_t *iters, int64_t *changed_trace, void *ws, size_t ws_bytes,
-                             void *stream);
+                             int32_t *iters, int64_t *changed_trace, double *objective, void *ws,
+                             size_t ws_bytes, void *stream);
 size_t kkm_feature_lloyd_workspace_bytes(int64_t n, int64_t f, int32_t k);
 
 /* K-means++ seeding (D^2 sampling, the K-means++ of Sec. 2.1) on feature rows

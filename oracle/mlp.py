@@ -110,19 +110,6 @@ def adam_step(theta, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def init_params(d, h1=512, h2=512, out=256, seed=0):
-    """Initial parameters: W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)), b = 0 (float32 values)."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    for s in param_shapes(d, h1, h2, out):
-        if len(s) == 2:
-            lim = 1.0 / math.sqrt(s[1])
-            parts.append(rng.uniform(-lim, lim, s))
-        else:
-            parts.append(np.zeros(s))
-    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
-
-
 def lloyd_step(F, k, labels):
     """One Lloyd step with explicit centroids on feature rows F.
     Returns (labels_out, D, n_changed)."""

@@ -10,7 +10,7 @@ from ._binding import (BF16, EMPTY_INF, EMPTY_ZERO_CENTROID, EXPORTS, F32, FP8_R
                        iterate_workspace_bytes, kkm_fit, kkm_fit_ex, kkm_gram, kkm_iterate,
                        kkm_timing_enable, kkm_timing_read, lib, mlp_param_count, kkm_mlp_forward,
                        kkm_mlp_loss_grad, kkm_mlp_adam, kkm_mlp_train, kkm_feature_lloyd,
-                       kkm_feature_kmeanspp)
+                       kkm_feature_kmeanspp, kkm_mlp_train_fresh)
 
 __all__ = ["kkm_gram", "kkm_iterate", "kkm_fit", "kkm_fit_ex", "kkm_timing_enable",
            "kkm_timing_read", "mlp_param_count", "kkm_mlp_forward", "kkm_mlp_loss_grad",

@@ -27,6 +27,7 @@ EXPORTS = ("kkm_gram", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_w
            "kkm_mlp_forward_workspace_bytes", "kkm_mlp_loss_grad", "kkm_mlp_train_workspace_bytes",
            "kkm_mlp_adam", "kkm_mlp_train", "kkm_feature_lloyd", "kkm_feature_lloyd_workspace_bytes",
            "kkm_feature_kmeanspp", "kkm_feature_kmeanspp_workspace_bytes",
+           "kkm_mlp_train_fresh", "kkm_mlp_train_fresh_workspace_bytes",
            "kkm_timing_enable", "kkm_timing_read", "kkm_last_error")
 
 
@@ -83,11 +84,18 @@ def lib():
         L.kkm_mlp_train.restype = ctypes.c_int
         L.kkm_mlp_train.argtypes = [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _vp, _i64, _i64, _vp,
                                     _i64, _vp, _i64, _i32, _i32, _d, _d, _d, _d, _vp, _vp, _sz, _vp]
+        L.kkm_mlp_train_fresh_workspace_bytes.restype = _sz
+        L.kkm_mlp_train_fresh_workspace_bytes.argtypes = [_i64, _i64, _i64, _i64, _i64]
+        L.kkm_mlp_train_fresh.restype = ctypes.c_int
+        L.kkm_mlp_train_fresh.argtypes = [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _vp, _i64, _i64,
+                                          _i32, _i32, _i32, _d, _d, _i32, _d, _d, _d, _d, _vp, _vp,
+                                          _sz, _vp]
         L.kkm_feature_lloyd_workspace_bytes.restype = _sz
         L.kkm_feature_lloyd_workspace_bytes.argtypes = [_i64, _i64, _i32]
         L.kkm_feature_lloyd.restype = ctypes.c_int
         L.kkm_feature_lloyd.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _i32, _vp,
-                                        ctypes.POINTER(_i32), _vp, _vp, _sz, _vp]
+                                        ctypes.POINTER(_i32), _vp, ctypes.POINTER(_d), _vp, _sz,
+                                        _vp]
         L.kkm_feature_kmeanspp_workspace_bytes.restype = _sz
         L.kkm_feature_kmeanspp_workspace_bytes.argtypes = [_i64, _i64, _i32]
         L.kkm_feature_kmeanspp.restype = ctypes.c_int
@@ -345,8 +353,29 @@ def kkm_mlp_train(params, m, v, Xtrain, Ktrain, batch_idx, t0=0, lr=1e-3, beta1=
     return losses[:steps]
 
 
-def kkm_feature_lloyd(F, k, labels0, max_iter=100, labels_out=None, ws=None):
-    """Lloyd on feature rows.  Returns (labels_out, iters, changed_trace)."""
+def kkm_mlp_train_fresh(params, m, v, Xtrain, B, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1,
+                        t0=0, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, h1=512, h2=512, out=256,
+                        ws=None):
+    """Train on consecutive batches of B rows of Xtrain (Xtrain.shape[0] // B steps),
+    each batch's kernel values computed by the Gram kernel.  Returns the per-step
+    losses (device float64)."""
+    _dev(Xtrain, torch.float32, "Xtrain", 2)
+    mt, d, ldx = _rows(Xtrain, "Xtrain")
+    steps = mt // B
+    losses = torch.empty(max(steps, 1), dtype=torch.float64, device=Xtrain.device)
+    need = int(lib().kkm_mlp_train_fresh_workspace_bytes(B, d, h1, h2, out))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=Xtrain.device)
+    _check(lib().kkm_mlp_train_fresh(_ptr(params), _ptr(m), _ptr(v), d, h1, h2, out, _ptr(Xtrain),
+                                     ldx, B, steps, t0, kernel, gamma, coef0, degree, lr, beta1,
+                                     beta2, eps, _ptr(losses), _ptr(ws), ws.numel(), _stream()))
+    return losses[:steps]
+
+
+def kkm_feature_lloyd(F, k, labels0, max_iter=100, labels_out=None, ws=None,
+                      return_objective=False):
+    """Lloyd on feature rows.  Returns (labels_out, iters, changed_trace), plus the
+    feature-space objective of the last step when return_objective is set."""
     import numpy as np
     _dev(F, torch.float32, "F", 2)
     _dev(labels0, torch.int32, "labels0", 1)
@@ -357,10 +386,13 @@ def kkm_feature_lloyd(F, k, labels0, max_iter=100, labels_out=None, ws=None):
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=F.device)
     it = _i32()
+    obj = _d()
     tr = np.zeros(max(max_iter, 1), dtype=np.int64)
     _check(lib().kkm_feature_lloyd(_ptr(F), n, f, ldf, k, _ptr(labels0), max_iter, _ptr(labels_out),
-                                   ctypes.byref(it), tr.ctypes.data_as(_vp), _ptr(ws), ws.numel(),
-                                   _stream()))
+                                   ctypes.byref(it), tr.ctypes.data_as(_vp), ctypes.byref(obj),
+                                   _ptr(ws), ws.numel(), _stream()))
+    if return_objective:
+        return labels_out, int(it.value), tr[:int(it.value)], obj.value
     return labels_out, int(it.value), tr[:int(it.value)]
 
 

@@ -44,6 +44,14 @@ struct TimedSpan {
 TimedSpan timing_begin(int cls, hipStream_t stream);
 void timing_end(const TimedSpan &span, hipStream_t stream);
 
+// ---------------------------------------------------------------- shared launchers
+
+size_t gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec);
+kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t kernel,
+                       double gamma, double coef0, int32_t degree, int32_t gram_prec,
+                       int32_t k_store, void *K, int64_t ldk, float *diagK, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+
 // ---------------------------------------------------------------- workspace carving
 
 struct Carver {

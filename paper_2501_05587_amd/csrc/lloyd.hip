@@ -28,6 +28,7 @@ struct LloydWs {
     uint32_t *ticket;
     float *fn, *Cp, *C, *cn, *G;
     int32_t *lab[2];
+    double *part, *obj;
 };
 
 LloydWs carve_lloyd(void *base, int64_t n, int64_t f, int32_t k, size_t *bytes) {
@@ -51,6 +52,8 @@ LloydWs carve_lloyd(void *base, int64_t n, int64_t f, int32_t k, size_t *bytes) 
     w.G = c.take<float>((size_t)(n * k));
     w.lab[0] = c.take<int32_t>((size_t)n);
     w.lab[1] = c.take<int32_t>((size_t)n);
+    w.part = c.take<double>((size_t)((n + 255) / 256));
+    w.obj = c.take<double>(1);
     if (bytes) *bytes = c.bytes();
     return w;
 }
@@ -119,14 +122,20 @@ __global__ __launch_bounds__(256) void centroid_finalize(const float *Cp, int64_
     if (threadIdx.x == 0) cn[c] = sh[0];
 }
 
+// Also writes, per block, the sum of the chosen (smallest) distances in FP64
+// (part, nullable): summed over blocks it is sum_i min_c d_ic, which equals the
+// objective of the new labels once no label changes.
 __global__ __launch_bounds__(256) void feature_assign(const float *G, const float *fn,
                                                       const float *cn, const int32_t *offsets,
                                                       int64_t n, int32_t k,
                                                       const int32_t *labels_in,
-                                                      int32_t *labels_out, int64_t *changed) {
+                                                      int32_t *labels_out, int64_t *changed,
+                                                      double *part) {
     __shared__ long long wc[4];
+    __shared__ double wd[4];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     long long ch = 0;
+    double dmin = 0.0;
     if (i < n) {
         float best = __builtin_inff();
         int32_t arg = labels_in[i];
@@ -140,14 +149,33 @@ __global__ __launch_bounds__(256) void feature_assign(const float *G, const floa
         }
         labels_out[i] = arg;
         ch = (arg != labels_in[i]);
+        dmin = (double)fmaxf(best, 0.0f);
     }
     ch = wave_sum(ch);
-    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = ch;
+    dmin = wave_sum(dmin);
+    if ((threadIdx.x & 63) == 0) {
+        wc[threadIdx.x >> 6] = ch;
+        wd[threadIdx.x >> 6] = dmin;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         const long long t = wc[0] + wc[1] + wc[2] + wc[3];
         if (t) atomicAdd((unsigned long long *)changed, (unsigned long long)t);
+        if (part) part[blockIdx.x] = (wd[0] + wd[1]) + (wd[2] + wd[3]);
     }
+}
+
+__global__ __launch_bounds__(256) void sum_blocks(const double *part, int64_t np, double *out) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += 256) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
 }
 
 // ---------------------------------------------------------------- k-means++ seeding
@@ -334,7 +362,7 @@ extern "C" kkm_status kkm_feature_kmeanspp(const float *F, int64_t n, int64_t f,
     g.ldc = k;
     KKM_TRY(gemm_launch(GEMM_F32, true, true, EPI_STORE, g, s));
     hipLaunchKernelGGL(feature_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, fn,
-                       cn, offs, n, k, lab_in, labels_out, changed);
+                       cn, offs, n, k, lab_in, labels_out, changed, nullptr);
     KKM_HIP(hipGetLastError());
     return KKM_OK;
 }
@@ -349,7 +377,8 @@ extern "C" size_t kkm_feature_lloyd_workspace_bytes(int64_t n, int64_t f, int32_
 extern "C" kkm_status kkm_feature_lloyd(const float *F, int64_t n, int64_t f, int64_t ldf,
                                         int32_t k, const int32_t *labels0, int32_t max_iter,
                                         int32_t *labels_out, int32_t *iters,
-                                        int64_t *changed_trace, void *ws, size_t ws_bytes,
+                                        int64_t *changed_trace, double *objective, void *ws,
+                                        size_t ws_bytes,
                                         void *stream) {
     if (n < 1 || f < 1 || ldf < f || k < 1 || k > n || max_iter < 0 || !F || !labels0 ||
         !labels_out || !iters) {
@@ -405,7 +434,8 @@ extern "C" kkm_status kkm_feature_lloyd(const float *F, int64_t n, int64_t f, in
         g.ldc = k;
         KKM_TRY(gemm_launch(GEMM_F32, true, true, EPI_STORE, g, s));
         hipLaunchKernelGGL(feature_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.G,
-                           w.fn, w.cn, w.offsets, n, k, w.lab[cur], w.lab[cur ^ 1], w.changed);
+                           w.fn, w.cn, w.offsets, n, k, w.lab[cur], w.lab[cur ^ 1], w.changed,
+                           w.part);
         KKM_HIP(hipGetLastError());
         KKM_HIP(hipMemcpyAsync(&hc, w.changed, sizeof hc, hipMemcpyDeviceToHost, s));
         KKM_HIP(hipStreamSynchronize(s));
@@ -417,7 +447,15 @@ extern "C" kkm_status kkm_feature_lloyd(const float *F, int64_t n, int64_t f, in
         }
     }
     KKM_HIP(hipMemcpyAsync(labels_out, w.lab[cur], (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    double obj = 0.0;
+    if (objective && t > 0) {
+        // sum_i min_c d_ic of the last step (the objective of labels_out when it changed nothing)
+        hipLaunchKernelGGL(sum_blocks, dim3(1), dim3(256), 0, s, w.part, (n + 255) / 256, w.obj);
+        KKM_HIP(hipGetLastError());
+        KKM_HIP(hipMemcpyAsync(&obj, w.obj, sizeof obj, hipMemcpyDeviceToHost, s));
+    }
     KKM_HIP(hipStreamSynchronize(s));
     *iters = t;
+    if (objective) *objective = (t > 0) ? obj : __builtin_nan("");
     return KKM_OK;
 }

@@ -345,3 +345,53 @@ extern "C" kkm_status kkm_mlp_train(float *params, float *adam_m, float *adam_v,
     }
     return KKM_OK;
 }
+
+extern "C" size_t kkm_mlp_train_fresh_workspace_bytes(int64_t B, int64_t d, int64_t h1,
+                                                      int64_t h2, int64_t out) {
+    const Dims m{d, h1, h2, out};
+    if (!dims_ok(m) || B < 1) return 0;
+    size_t bytes = 0;
+    carve_train(nullptr, m, B, &bytes);
+    return bytes + gram_workspace_bytes(B, d, KKM_F32);
+}
+
+extern "C" kkm_status kkm_mlp_train_fresh(float *params, float *adam_m, float *adam_v, int64_t d,
+                                          int64_t h1, int64_t h2, int64_t out,
+                                          const float *Xtrain, int64_t ldx, int64_t B,
+                                          int32_t steps, int32_t t0, int32_t kernel_type,
+                                          double gamma, double coef0, int32_t degree, double lr,
+                                          double beta1, double beta2, double eps,
+                                          double *loss_trace, void *ws, size_t ws_bytes,
+                                          void *stream) {
+    const Dims m{d, h1, h2, out};
+    KKM_TRY(check_dims(m));
+    if (B < 1 || steps < 0 || t0 < 0 || ldx < d || !params || !adam_m || !adam_v || !Xtrain ||
+        !loss_trace) {
+        set_error("kkm_mlp_train_fresh: bad sizes or NULL pointer");
+        return KKM_ERR_ARG;
+    }
+    if (kernel_type != KKM_LINEAR && kernel_type != KKM_POLY && kernel_type != KKM_GAUSS) {
+        set_error("kkm_mlp_train_fresh: unknown kernel type %d", kernel_type);
+        return KKM_ERR_ARG;
+    }
+    size_t need = 0;
+    TrainWs w = carve_train(ws, m, B, &need);
+    const size_t gws = gram_workspace_bytes(B, d, KKM_F32);
+    if (!ws || ws_bytes < need + gws) {
+        set_error("kkm_mlp_train_fresh: workspace of %zu bytes is smaller than %zu", ws_bytes,
+                  need + gws);
+        return KKM_ERR_NOMEM;
+    }
+    void *gram_ws = static_cast<char *>(ws) + need;
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t st = 0; st < steps; ++st) {
+        // step st trains on rows st*B .. st*B+B-1 and their kernel values, computed now
+        const float *XB = Xtrain + (int64_t)st * B * ldx;
+        KKM_TRY(gram_launch(XB, B, d, ldx, kernel_type, gamma, coef0, degree, KKM_F32, KKM_F32,
+                            w.KB, B, w.Z1 /* diag(K), unused */, gram_ws, gws, s));
+        KKM_TRY(loss_grad(params, m, XB, ldx, w.KB, B, B, w, w.grad, loss_trace + st, s));
+        KKM_TRY(kkm_mlp_adam(params, adam_m, adam_v, w.grad, m.count(), t0 + st + 1, lr, beta1,
+                             beta2, eps, stream));
+    }
+    return KKM_OK;
+}

@@ -7,6 +7,8 @@ import math
 import numpy as np
 import pytest
 
+import datagen
+
 from oracle import mlp
 
 DIMS = dict(d=6, h1=9, h2=7, out=5)
@@ -14,7 +16,7 @@ DIMS = dict(d=6, h1=9, h2=7, out=5)
 
 def small_problem(seed=0, B=8):
     rng = np.random.default_rng(seed)
-    theta = mlp.init_params(**DIMS, seed=seed).astype(np.float64)
+    theta = datagen.mlp_init_params(**DIMS, seed=seed).astype(np.float64)
     theta += rng.normal(0, 0.05, theta.shape)  # non-zero biases too
     X = rng.normal(0, 1, (B, DIMS["d"]))
     A = rng.normal(0, 1, (B, B))
