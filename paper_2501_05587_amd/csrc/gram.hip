@@ -21,164 +21,13 @@
 //         v_mfma_f32_32x32x16_fp8_fp8; B_ij = s_i s_j sum_l q_il q_jl.
 // For BF16/FP8 the squared norms of the Gaussian are taken from the same
 // rounded values.  K is stored as FP32 or bfloat16 (k_store).
-#include "kkm_common.h"
+#include "gram_tile.h"
 
 namespace kkm {
 
 namespace {
 
-constexpr int GM = 128;       // tile edge (rows = columns)
-constexpr int GTHREADS = 256; // 4 waves as 2 x 2, each owns a 64 x 64 sub-tile
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    // round to nearest even on the dropped 16 bits; a NaN stays a (quiet) NaN
-    const uint32_t u = __float_as_uint(f);
-    const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-    return (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? ((u >> 16) | 0x40) : r);
-}
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// ---------------------------------------------------------------- shared epilogue
-
-struct Epi {
-    int64_t n, ldk;
-    int kernel;
-    float gamma, coef0;
-    int degree;
-    const float *nrm;    // squared norms (Gaussian)
-    const float *scale;  // per-row scales (FP8), else null
-    void *K;
-    float *diag;
-    int vec_k;           // K rows aligned for 4-element stores
-};
-
-__device__ __forceinline__ float kappa_from_dot(float b, float ni, float nj, int kernel,
-                                                float gamma, float coef0, int degree) {
-    if (kernel == KKM_GAUSS) {
-        float sq = fmaxf(ni + nj - 2.0f * b, 0.0f);
-        return expf(-gamma * sq);
-    }
-    if (kernel == KKM_POLY) {
-        float t = fmaf(gamma, b, coef0);
-        float v = t;
-        for (int r = 1; r < degree; ++r) v *= t;
-        return v;
-    }
-    return b;
-}
-
-template <typename OUT> struct Store;
-template <> struct Store<float> {
-    static __device__ __forceinline__ float round(float v) { return v; }
-    static __device__ __forceinline__ void one(void *K, int64_t idx, float v) {
-        static_cast<float *>(K)[idx] = v;
-    }
-    static __device__ __forceinline__ void four(void *K, int64_t idx, const float v[4]) {
-        f32x4 w = {v[0], v[1], v[2], v[3]};
-        *reinterpret_cast<f32x4 *>(static_cast<float *>(K) + idx) = w;
-    }
-};
-template <> struct Store<uint16_t> {
-    static __device__ __forceinline__ float round(float v) { return bf16_to_f32(f32_to_bf16(v)); }
-    static __device__ __forceinline__ void one(void *K, int64_t idx, float v) {
-        static_cast<uint16_t *>(K)[idx] = f32_to_bf16(v);
-    }
-    static __device__ __forceinline__ void four(void *K, int64_t idx, const float v[4]) {
-        uint2 w;
-        w.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
-        w.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
-        *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(K) + idx) = w;
-    }
-};
-
-// Writes one wave's 64 x 64 sub-tile (2 x 2 blocks of 32 x 32 accumulators).
-// Accumulator register r of lane l holds output row 8*(r/4) + 4*(l/32) + r%4
-// and column l%32 of its 32 x 32 block.
-template <typename OUT>
-__device__ __forceinline__ void epilogue(const Epi &e, const f32x16 (&acc)[2][2], int64_t m0,
-                                         int64_t n0, bool diag_tile, int wr, int wc, int lane) {
-    const int half = lane >> 5, l32 = lane & 31;
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi) {
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni) {
-            const int64_t gj = n0 + wc * 64 + ni * 32 + l32;
-            const bool jin = gj < e.n;
-            const float nrm_j = (e.kernel == KKM_GAUSS && jin) ? e.nrm[gj] : 0.f;
-            const float s_j = (e.scale && jin) ? e.scale[gj] : 1.f;
-#pragma unroll
-            for (int rg = 0; rg < 4; ++rg) {
-                const int64_t gi0 = m0 + wr * 64 + mi * 32 + 8 * rg + 4 * half;
-                float v[4], b[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t gi = gi0 + r;
-                    const bool iin = gi < e.n;
-                    const float nrm_i = (e.kernel == KKM_GAUSS && iin) ? e.nrm[gi] : 0.f;
-                    b[r] = acc[mi][ni][4 * rg + r];
-                    if (e.scale) b[r] *= (iin ? e.scale[gi] : 1.f) * s_j;
-                    v[r] = kappa_from_dot(b[r], nrm_i, nrm_j, e.kernel, e.gamma, e.coef0,
-                                          e.degree);
-                }
-                if (!jin) continue;
-                if (!diag_tile) {
-                    // K[gi][gj]: the 32 lanes of a half write 32 consecutive entries of a row
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (gi0 + r < e.n) Store<OUT>::one(e.K, (gi0 + r) * e.ldk + gj, v[r]);
-                    // mirror K[gj][gi0 .. gi0+3]: four consecutive entries of row gj
-                    if (e.vec_k && gi0 + 3 < e.n) {
-                        Store<OUT>::four(e.K, gj * e.ldk + gi0, v);
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (gi0 + r < e.n) Store<OUT>::one(e.K, gj * e.ldk + gi0 + r, v[r]);
-                    }
-                } else {
-                    // diagonal tile: the upper triangle is the source of truth
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t gi = gi0 + r;
-                        if (gi >= e.n || gi > gj) continue;
-                        if (gi == gj) {
-                            // kappa(x, x) = exp(0) = 1 exactly; a non-finite row stays visible
-                            const float dv = (e.kernel == KKM_GAUSS)
-                                                 ? (isfinite(b[r]) ? 1.0f : __builtin_nanf(""))
-                                                 : Store<OUT>::round(v[r]);
-                            Store<OUT>::one(e.K, gi * e.ldk + gi, dv);
-                            e.diag[gi] = dv;
-                        } else {
-                            Store<OUT>::one(e.K, gi * e.ldk + gj, v[r]);
-                            Store<OUT>::one(e.K, gj * e.ldk + gi, v[r]);
-                        }
-                    }
-                }
-            }
-        }
-    }
-}
-
-// Upper-triangle tile t -> (bi, bj), bi <= bj, column by column.
-__device__ __forceinline__ void tile_coords(int64_t t, int64_t &bi, int64_t &bj) {
-    int64_t j = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while (j * (j + 1) / 2 > t) --j;
-    while ((j + 1) * (j + 2) / 2 <= t) ++j;
-    bj = j;
-    bi = t - j * (j + 1) / 2;
-}
-
-// Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous
-// range of tiles so that tiles sharing an operand panel share an L2.
-__device__ __forceinline__ bool tile_of_block(int64_t ntiles, int64_t per_xcd, int64_t &bi,
-                                              int64_t &bj) {
-    const int64_t pid = blockIdx.x;
-    const int64_t t = (pid % 8) * per_xcd + pid / 8;
-    if (t >= ntiles) return false;
-    tile_coords(t, bi, bj);
-    return true;
-}
+using namespace gt;
 
 // ---------------------------------------------------------------- FP32 product
 
@@ -289,121 +138,13 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_f32_mfma(F32Args a) {
 
 // ---------------------------------------------------------------- BF16 / FP8 product
 
-// A slab is 128 bytes of every row (64 bf16 or 128 fp8), staged in LDS with a
-// 16-byte pad.  The quantised matrix has its rows zero-padded to a whole
-// number of slabs, so the loads need no column checks.
-constexpr int SLAB = 128;
-constexpr int SLD = SLAB + 16;
-
-struct LowpArgs {
-    const unsigned char *Xq;  // [n][ldq_bytes]
-    int64_t ldq_bytes;
-    int64_t nslab;
-    int64_t ntiles, per_xcd;
-    Epi e;
-};
-
 template <int PREC, typename OUT>
-__global__ __launch_bounds__(GTHREADS, 2) void gram_lowp_mfma(LowpArgs a) {
-    __shared__ __attribute__((aligned(16))) unsigned char lds[2][2][GM * SLD];
+__global__ __launch_bounds__(GTHREADS, 2) void gram_lowp_mfma(LowpTile a, int64_t ntiles,
+                                                              int64_t per_xcd) {
+    __shared__ __attribute__((aligned(16))) LowpLds lds;
     int64_t bi, bj;
-    if (!tile_of_block(a.ntiles, a.per_xcd, bi, bj)) return;
-    const int64_t m0 = bi * GM, n0 = bj * GM;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int ld_row = tid >> 3;          // 8 threads x 16 bytes per row slab
-    const int ld_col = (tid & 7) * 16;
-
-    uint4 ra[4], rb[4];
-    auto gload = [&](int64_t slab) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t r1 = m0 + ld_row + 32 * u, r2 = n0 + ld_row + 32 * u;
-            ra[u] = make_uint4(0, 0, 0, 0);
-            rb[u] = make_uint4(0, 0, 0, 0);
-            if (r1 < a.e.n)
-                ra[u] = *reinterpret_cast<const uint4 *>(a.Xq + r1 * a.ldq_bytes + slab * SLAB + ld_col);
-            if (r2 < a.e.n)
-                rb[u] = *reinterpret_cast<const uint4 *>(a.Xq + r2 * a.ldq_bytes + slab * SLAB + ld_col);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            *reinterpret_cast<uint4 *>(&lds[buf][0][(ld_row + 32 * u) * SLD + ld_col]) = ra[u];
-            *reinterpret_cast<uint4 *>(&lds[buf][1][(ld_row + 32 * u) * SLD + ld_col]) = rb[u];
-        }
-    };
-
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-    gload(0);
-    sstore(0);
-    __syncthreads();
-
-    // Lane half h of a 32x32x16 MFMA supplies k = 8h .. 8h+7.  Within a slab the
-    // same permutation is used for both operands: MFMA s takes, from half h,
-    // the 8 (bf16) or 8 (fp8) elements starting at byte 64h + 16s (bf16) or
-    // 64h + 8s (fp8), so each lane reads 64 consecutive bytes of its row.
-    const int half = lane >> 5;
-    const int l32 = lane & 31;
-    for (int64_t kt = 0; kt < a.nslab; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < a.nslab) gload(kt + 1);
-        const unsigned char *As = lds[buf][0];
-        const unsigned char *Bs = lds[buf][1];
-        uint4 av[2][4], bv[2][4];
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-            const unsigned char *pa = As + (wr * 64 + mi * 32 + l32) * SLD + half * 64;
-            const unsigned char *pb = Bs + (wc * 64 + mi * 32 + l32) * SLD + half * 64;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                av[mi][q] = *reinterpret_cast<const uint4 *>(pa + 16 * q);
-                bv[mi][q] = *reinterpret_cast<const uint4 *>(pb + 16 * q);
-            }
-        }
-        if constexpr (PREC == KKM_BF16) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 2; ++ni) {
-                        bf16x8 x, y;
-                        __builtin_memcpy(&x, &av[mi][s], 16);
-                        __builtin_memcpy(&y, &bv[ni][s], 16);
-                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc[mi][ni], 0, 0, 0);
-                    }
-        } else {
-#pragma unroll
-            for (int s = 0; s < 8; ++s)
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 2; ++ni) {
-                        const uint4 &p = av[mi][s >> 1];
-                        const uint4 &q = bv[ni][s >> 1];
-                        const long x = (s & 1) ? (long)(((uint64_t)p.w << 32) | p.z)
-                                               : (long)(((uint64_t)p.y << 32) | p.x);
-                        const long y = (s & 1) ? (long)(((uint64_t)q.w << 32) | q.z)
-                                               : (long)(((uint64_t)q.y << 32) | q.x);
-                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(x, y, acc[mi][ni], 0, 0, 0);
-                    }
-        }
-        if (kt + 1 < a.nslab) sstore(buf ^ 1);
-        __syncthreads();
-    }
-    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane);
+    if (!tile_of_block(ntiles, per_xcd, bi, bj)) return;
+    lowp_tile<PREC, OUT>(a, bi, bj, lds);
 }
 
 // ---------------------------------------------------------------- prologues
@@ -421,74 +162,17 @@ __global__ __launch_bounds__(256) void row_sqnorms(const float *X, int64_t n, in
     if (lane == 0) nrm[row] = s;
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
-    return v;
-}
-
-// Rounds each row to the product's input type and records the squared norm of
-// the rounded row (and, for FP8, the row scale).  One wave per row; lane l
-// handles elements 4l .. 4l+3 of every 256-element group; rows are zero-padded
-// to dpad elements.
+// One wave per row: rounds the row and records its squared norm (and scale).
 template <int PREC>
 __global__ __launch_bounds__(256) void quantize_rows(const float *X, int64_t n, int64_t d,
                                                      int64_t ldx, int64_t dpad,
                                                      unsigned char *Xq, float *nrm,
                                                      float *scale) {
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
     if (row >= n) return;
-    const float *x = X + row * ldx;
-    float inv = 1.f, s = 1.f;
-    if (PREC == KKM_FP8_ROWSCALED) {
-        float m = 0.f;
-        for (int64_t l = lane; l < d; l += kWave) m = fmaxf(m, fabsf(x[l]));
-        m = wave_max(m);
-        if (m > 0.f && isfinite(m)) {
-            s = m / 448.0f;
-            inv = 448.0f / m;
-        } else if (!isfinite(m)) {
-            s = m;  // propagate a non-finite row
-        }
-        if (lane == 0) scale[row] = s;
-    }
-    float acc = 0.f;
-    for (int64_t l0 = 4 * lane; l0 < dpad; l0 += 4 * kWave) {
-        float v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = (l0 + u < d) ? x[l0 + u] : 0.f;
-        if (PREC == KKM_BF16) {
-            uint16_t h[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                h[u] = f32_to_bf16(v[u]);
-                const float r = bf16_to_f32(h[u]);
-                acc = fmaf(r, r, acc);
-            }
-            uint2 w;
-            w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-            w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-            *reinterpret_cast<uint2 *>(Xq + row * dpad * 2 + l0 * 2) = w;
-        } else {
-            float y[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) y[u] = fminf(fmaxf(v[u] * inv, -448.0f), 448.0f);
-            int p = __builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
-            p = __builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], p, true);
-            const float q0 = __builtin_amdgcn_cvt_f32_fp8(p, 0);
-            const float q1 = __builtin_amdgcn_cvt_f32_fp8(p, 1);
-            const float q2 = __builtin_amdgcn_cvt_f32_fp8(p, 2);
-            const float q3 = __builtin_amdgcn_cvt_f32_fp8(p, 3);
-            acc = fmaf(q0, q0, acc);
-            acc = fmaf(q1, q1, acc);
-            acc = fmaf(q2, q2, acc);
-            acc = fmaf(q3, q3, acc);
-            *reinterpret_cast<int *>(Xq + row * dpad + l0) = p;
-        }
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) nrm[row] = (PREC == KKM_FP8_ROWSCALED) ? s * s * acc : acc;
+    const int64_t eb = (PREC == KKM_BF16) ? 2 : 1;
+    quantize_row<PREC>(X + row * ldx, d, dpad, Xq + row * dpad * eb, nrm + row, scale + row,
+                       threadIdx.x & 63);
 }
 
 int64_t padded_d(int64_t d, int32_t gram_prec) {
@@ -580,24 +264,22 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
         hipLaunchKernelGGL(quantize_rows<KKM_FP8_ROWSCALED>, dim3(qgrid), dim3(256), 0, stream,
                            X, n, d, ldx, dpad, Xq, nrm, scale);
     KKM_HIP(hipGetLastError());
-    LowpArgs a;
+    LowpTile a;
     a.Xq = Xq;
     a.ldq_bytes = dpad * eb;
     a.nslab = dpad * eb / SLAB;
-    a.ntiles = ntiles;
-    a.per_xcd = per_xcd;
     a.e = e;
     if (gram_prec == KKM_FP8_ROWSCALED) a.e.scale = scale;
     const TimedSpan span = timing_begin(TK_GRAM, stream);
     const dim3 g((unsigned)grid), b(GTHREADS);
     if (gram_prec == KKM_BF16 && k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, float>), g, b, 0, stream, a);
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, float>), g, b, 0, stream, a, ntiles, per_xcd);
     else if (gram_prec == KKM_BF16)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, uint16_t>), g, b, 0, stream, a);
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, uint16_t>), g, b, 0, stream, a, ntiles, per_xcd);
     else if (k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, float>), g, b, 0, stream, a);
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, float>), g, b, 0, stream, a, ntiles, per_xcd);
     else
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, uint16_t>), g, b, 0, stream, a);
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, uint16_t>), g, b, 0, stream, a, ntiles, per_xcd);
     KKM_HIP(hipGetLastError());
     timing_end(span, stream);
     return KKM_OK;

@@ -1,0 +1,76 @@
+// One reassignment step for a set of independent clustering problems.
+// Internal to the library.
+#pragma once
+
+#include "kkm_common.h"
+
+namespace kkm {
+
+// One clustering problem as the step kernels see it: its kernel matrix, its
+// workspace (V in CSR form, partial sums) and where its outputs go.
+struct Inst {
+    int64_t n;          // points
+    int32_t k;          // clusters
+    int32_t empty_policy;
+    int64_t L;          // CSR positions per sweep chunk
+    int64_t nblk;       // 256-point label blocks
+    int64_t ldp;        // row stride of the segment partials
+    int64_t nstrip;     // sweep column strips (256 lanes x 16 bytes each)
+    int64_t nws;        // 64-lane wave strips of columns
+    const void *K;      // [n, ldk] FP32 or bfloat16
+    int64_t ldk;
+    const float *diag;  // [n]
+    int64_t lab_off;    // first label of this problem in the label arrays
+    // workspace
+    int32_t *perm, *offsets, *counts, *blk_hist, *blk_bad, *err;
+    float *P, *Zp, *ctilde;
+    double *Jpart;
+    uint32_t *ticket;
+    // outputs of the step
+    int32_t *counts_out;
+    int64_t *n_changed;
+    double *J_in;
+    float *D_out, *ctilde_out;  // nullable
+};
+
+// A set of problems: `one` passed by value (table == nullptr), or a device
+// table of `count` problems whose blocks / clusters / sweep items are laid end
+// to end (prefix arrays of count + 1 entries).  active (nullable): a problem
+// with active[b] == 0 is skipped.
+struct InstSet {
+    const Inst *table;
+    const int32_t *active;
+    const int64_t *blk_start, *cl_start, *item_start;
+    int32_t count;
+    Inst one;
+};
+
+struct InstGeom {
+    int64_t n;
+    int32_t k;
+    int64_t L, nblk, nchunk, slots, ldp, nws_max;
+};
+
+// Geometry of a problem; L = 0 picks the default chunk length.
+InstGeom inst_geometry(int64_t n, int32_t k, int64_t L);
+size_t inst_workspace_bytes(const InstGeom &g);
+// Carves a problem's workspace from `base` and fills its geometry and
+// workspace fields in `in` (when non-null); `bytes` receives the size.
+void inst_carve(void *base, const InstGeom &g, Inst *in, size_t *bytes);
+int64_t inst_sweep_items(const InstGeom &g, int32_t k_store);
+// Sets the strip counts that depend on the element type of K.
+void inst_set_store(Inst *in, int32_t k_store);
+
+// The six kernels of one step over the whole set.  total_* are the grid sizes
+// (sums over the set); max_k sizes the dynamic LDS; vec: every K row is
+// 16-byte aligned.
+kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clusters,
+                       int64_t total_items, int32_t max_k, int32_t k_store, bool vec,
+                       const int32_t *labels_in, int32_t *labels_out, hipStream_t stream);
+
+kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
+                      int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,
+                      int32_t *offsets, int32_t *counts_out, int64_t *n_changed,
+                      uint32_t *ticket, hipStream_t stream);
+
+}  // namespace kkm

@@ -1,4 +1,5 @@
-// One reassignment step of the paper's Algorithm 2 on gfx950.
+// One reassignment step of the paper's Algorithm 2 on gfx950, for one
+// clustering problem or for many independent ones at once.
 //
 //   1. V from the labels (Sec. 4.1): cluster sizes by a reduction of the label
 //      array, then V in CSR form.  V's values are all 1/|c| within a row, so
@@ -17,9 +18,15 @@
 //      cluster-size histogram, the number of changed labels and the FP64
 //      objective of the input labels, fused in one pass over the points.
 //
+// Every kernel takes an instance set: either one problem passed by value, or a
+// device table of problems whose blocks are laid end to end in one grid (a
+// block finds its problem by binary search in a prefix array).  Problems
+// marked inactive are skipped, so a captured sequence of launches can be
+// replayed while problems converge one by one.
+//
 // No floating-point atomics are used: every reduction runs in a fixed order,
 // so a step is bitwise repeatable.
-#include "kkm_common.h"
+#include "iterate.h"
 
 namespace kkm {
 
@@ -27,86 +34,69 @@ namespace {
 
 constexpr int kPtsPerBlock = 256;          // points per block in the label kernels
 constexpr int kSweepThreads = 256;         // 4 waves
-constexpr int kSweepCols = kSweepThreads * 4;  // columns per sweep workgroup (float4 per lane)
-constexpr int kWaveCols = kWave * 4;       // columns per wave strip
 
-struct IterWs {
-    int32_t *perm;      // [n]      V's column indices: points grouped by cluster
-    int32_t *offsets;   // [k+1]    V's row pointers
-    int32_t *counts;    // [k]      cluster sizes of labels_in
-    int32_t *blk_hist;  // [k][nblk] per-block histograms, then exclusive prefixes
-    int32_t *blk_bad;   // [nblk]   per-block count of out-of-range labels
-    int32_t *err;       // [1]
-    float *P;           // [slots][ldp] per-segment column sums of K
-    float *Zp;          // [slots][nws] per-segment sums of the own-cluster entries
-    float *ctilde;      // [k]
-    double *Jpart;      // [nblk]
-    uint32_t *ticket;   // [1]
-};
-
-struct Geometry {
-    int64_t n;
-    int32_t k;
-    int64_t nblk;   // label blocks
-    int64_t L;      // rows of K per sweep chunk
-    int64_t nchunk;
-    int64_t slots;  // nchunk + k
-    int64_t ldp;
-    int64_t nws;    // wave strips of columns (FP32 K: the most; sizes the partial buffer)
-    int64_t nstrip; // workgroup strips of columns
-};
-
-Geometry make_geometry(int64_t n, int32_t k) {
-    Geometry g;
-    g.n = n;
-    g.k = k;
-    g.nblk = (n + kPtsPerBlock - 1) / kPtsPerBlock;
-    g.nstrip = (n + kSweepCols - 1) / kSweepCols;
-    g.nws = (n + kWaveCols - 1) / kWaveCols;
-    // chunk rows: the largest power of two in [64, 4096] that still gives
-    // about 8192 sweep workgroups (the partial sums cost slots * n floats)
-    int64_t L = 4096;
-    while (L > 64 && ((n + L - 1) / L) * g.nstrip < 8192) L >>= 1;
-    g.L = L;
-    g.nchunk = (n + L - 1) / L;
-    g.slots = g.nchunk + k;
-    g.ldp = (n + 63) & ~int64_t(63);
-    return g;
+// Reads of data that every lane of a workgroup takes from the same address and
+// that no kernel of the step writes, through the constant address space, so
+// they are scalar loads and the values stay in scalar registers.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) T *)(p);
+#else
+    return *p;  // the host pass only parses device functions
+#endif
 }
 
-IterWs carve(void *base, const Geometry &g, size_t *bytes) {
-    Carver c(base);
-    IterWs w;
-    w.perm = c.take<int32_t>((size_t)g.n);
-    w.offsets = c.take<int32_t>((size_t)g.k + 1);
-    w.counts = c.take<int32_t>((size_t)g.k);
-    w.blk_hist = c.take<int32_t>((size_t)g.k * (size_t)g.nblk);
-    w.blk_bad = c.take<int32_t>((size_t)g.nblk);
-    w.err = c.take<int32_t>(1);
-    w.P = c.take<float>((size_t)g.slots * (size_t)g.ldp);
-    w.Zp = c.take<float>((size_t)g.slots * (size_t)g.nws);
-    w.ctilde = c.take<float>((size_t)g.k);
-    w.Jpart = c.take<double>((size_t)g.nblk);
-    w.ticket = c.take<uint32_t>(1);
-    if (bytes) *bytes = c.bytes();
-    return w;
+__device__ __forceinline__ int32_t find_inst(const int64_t *start, int32_t count, int64_t g) {
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (uniform_load(start + mid) <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Problem b and the block index within it for a flattened grid position g.
+// MULTI selects the table form at compile time: a run-time choice between the
+// two sources would leave the problem's fields in vector registers.
+template <bool MULTI>
+__device__ __forceinline__ Inst locate(const InstSet &s, const int64_t *start, int64_t g,
+                                       int32_t &b, int64_t &local) {
+    if constexpr (MULTI) {
+        b = find_inst(start, s.count, g);
+        local = g - uniform_load(start + b);
+        return uniform_load(s.table + b);
+    } else {
+        b = 0;
+        local = g;
+        return s.one;
+    }
+}
+
+__device__ __forceinline__ bool inactive(const InstSet &s, int32_t b) {
+    return s.active && s.active[b] == 0;
 }
 
 // ---------------------------------------------------------------- 1. V in CSR form
 
 // Per-block label histogram (column-major [k][nblk]) and range check.
-__global__ __launch_bounds__(kPtsPerBlock) void v_block_hist(const int32_t *labels, int64_t n,
-                                                             int32_t k, int64_t nblk,
-                                                             int32_t *blk_hist,
-                                                             int32_t *blk_bad) {
+template <bool MULTI>
+__global__ __launch_bounds__(kPtsPerBlock) void v_block_hist(InstSet s, const int32_t *labels_all) {
     extern __shared__ int32_t sh[];  // [k] + 1
+    int32_t b;
+    int64_t lb;
+    const Inst in = locate<MULTI>(s, s.blk_start, blockIdx.x, b, lb);
+    if (inactive(s, b)) return;
+    const int32_t k = in.k;
+    const int32_t *labels = labels_all + in.lab_off;
     int32_t *hist = sh;
     int32_t *bad = sh + k;
     for (int c = threadIdx.x; c < k; c += blockDim.x) hist[c] = 0;
     if (threadIdx.x == 0) *bad = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * kPtsPerBlock + threadIdx.x;
-    if (i < n) {
+    const int64_t i = lb * kPtsPerBlock + threadIdx.x;
+    if (i < in.n) {
         const int32_t c = labels[i];
         if (c < 0 || c >= k)
             atomicAdd(bad, 1);
@@ -114,25 +104,27 @@ __global__ __launch_bounds__(kPtsPerBlock) void v_block_hist(const int32_t *labe
             atomicAdd(&hist[c], 1);
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < k; c += blockDim.x)
-        blk_hist[(int64_t)c * nblk + blockIdx.x] = hist[c];
-    if (threadIdx.x == 0) blk_bad[blockIdx.x] = *bad;
+    for (int c = threadIdx.x; c < k; c += blockDim.x) in.blk_hist[(int64_t)c * in.nblk + lb] = hist[c];
+    if (threadIdx.x == 0) in.blk_bad[lb] = *bad;
 }
 
-// One workgroup per cluster: exclusive prefix of its per-block counts (in
-// place) and its size.  Workgroup 0 also folds the range-check counts.
-__global__ __launch_bounds__(256) void v_cluster_scan(int32_t *blk_hist, int64_t nblk,
-                                                      int32_t *counts, const int32_t *blk_bad,
-                                                      int32_t *err) {
+// One workgroup per (problem, cluster): exclusive prefix of its per-block counts
+// (in place) and its size.  Cluster 0's workgroup also folds the range check.
+template <bool MULTI>
+__global__ __launch_bounds__(256) void v_cluster_scan(InstSet s) {
     __shared__ int32_t part[256];
     __shared__ int32_t carry;
-    const int c = blockIdx.x;
-    int32_t *row = blk_hist + (int64_t)c * nblk;
+    int32_t b;
+    int64_t c;
+    const Inst in = locate<MULTI>(s, s.cl_start, blockIdx.x, b, c);
+    if (inactive(s, b)) return;
+    const int64_t nblk = in.nblk;
+    int32_t *row = in.blk_hist + c * nblk;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int64_t base = 0; base < nblk; base += 256) {
-        const int64_t b = base + threadIdx.x;
-        const int32_t v = (b < nblk) ? row[b] : 0;
+        const int64_t i = base + threadIdx.x;
+        const int32_t v = (i < nblk) ? row[i] : 0;
         part[threadIdx.x] = v;
         __syncthreads();
         // Hillis-Steele inclusive scan over 256 entries
@@ -142,60 +134,64 @@ __global__ __launch_bounds__(256) void v_cluster_scan(int32_t *blk_hist, int64_t
             part[threadIdx.x] += add;
             __syncthreads();
         }
-        if (b < nblk) row[b] = carry + part[threadIdx.x] - v;
+        if (i < nblk) row[i] = carry + part[threadIdx.x] - v;
         __syncthreads();
         if (threadIdx.x == 255) carry += part[255];
         __syncthreads();
     }
-    if (threadIdx.x == 0) counts[c] = carry;
+    if (threadIdx.x == 0) in.counts[c] = carry;
     if (c == 0) {
-        int32_t s = 0;
-        for (int64_t b = threadIdx.x; b < nblk; b += 256) s += blk_bad[b];
-        part[threadIdx.x] = s;
+        int32_t t = 0;
+        for (int64_t i = threadIdx.x; i < nblk; i += 256) t += in.blk_bad[i];
+        part[threadIdx.x] = t;
         __syncthreads();
         if (threadIdx.x == 0) {
-            int32_t t = 0;
-            for (int u = 0; u < 256; ++u) t += part[u];
-            *err = t;
+            int32_t u = 0;
+            for (int w = 0; w < 256; ++w) u += part[w];
+            *in.err = u;
         }
     }
 }
 
-// Stable scatter of point indices into V's CSR order.  Block 0 also publishes
-// the row pointers and clears the step's counters.
-__global__ __launch_bounds__(kPtsPerBlock) void v_scatter(
-    const int32_t *labels, int64_t n, int32_t k, int64_t nblk, const int32_t *blk_hist,
-    const int32_t *counts, const int32_t *err, int32_t *perm, int32_t *offsets,
-    int32_t *counts_out, int64_t *n_changed, uint32_t *ticket) {
+// Stable scatter of point indices into V's CSR order.  Block 0 of each problem
+// also publishes the row pointers and clears the step's counters.
+template <bool MULTI>
+__global__ __launch_bounds__(kPtsPerBlock) void v_scatter(InstSet s, const int32_t *labels_all) {
     extern __shared__ int32_t sh[];  // off[k+1], wcnt[4][k]
+    int32_t b;
+    int64_t lb;
+    const Inst in = locate<MULTI>(s, s.blk_start, blockIdx.x, b, lb);
+    if (inactive(s, b)) return;
+    const int32_t k = in.k;
+    const int32_t *labels = labels_all + in.lab_off;
     int32_t *off = sh;
     int32_t *wcnt = sh + (k + 1);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    if (*err != 0) return;
+    if (*in.err != 0) return;
 
     // exclusive scan of the cluster sizes (k <= KKM_MAX_K; one thread, then share)
     if (tid == 0) {
         int32_t run = 0;
         for (int c = 0; c < k; ++c) {
             off[c] = run;
-            run += counts[c];
+            run += in.counts[c];
         }
         off[k] = run;
     }
     for (int c = tid; c < 4 * k; c += kPtsPerBlock) wcnt[c] = 0;
     __syncthreads();
-    if (blockIdx.x == 0) {
-        for (int c = tid; c <= k; c += kPtsPerBlock) offsets[c] = off[c];
-        for (int c = tid; c < k; c += kPtsPerBlock) counts_out[c] = 0;
+    if (lb == 0) {
+        for (int c = tid; c <= k; c += kPtsPerBlock) in.offsets[c] = off[c];
+        for (int c = tid; c < k; c += kPtsPerBlock) in.counts_out[c] = 0;
         if (tid == 0) {
-            *n_changed = 0;
-            *ticket = 0u;
+            *in.n_changed = 0;
+            *in.ticket = 0u;
         }
     }
 
-    const int64_t i = (int64_t)blockIdx.x * kPtsPerBlock + tid;
-    const bool valid = i < n;
+    const int64_t i = lb * kPtsPerBlock + tid;
+    const bool valid = i < in.n;
     const int32_t c = valid ? labels[i] : -1;
     // rank among equal labels earlier in this wave, by matching label groups
     uint64_t pending = __ballot(valid);
@@ -215,8 +211,8 @@ __global__ __launch_bounds__(kPtsPerBlock) void v_scatter(
     if (valid) {
         int32_t before = 0;
         for (int w = 0; w < wave; ++w) before += wcnt[w * k + c];
-        const int64_t pos = off[c] + blk_hist[(int64_t)c * nblk + blockIdx.x] + before + rank;
-        perm[pos] = (int32_t)i;
+        const int64_t pos = off[c] + in.blk_hist[(int64_t)c * in.nblk + lb] + before + rank;
+        in.perm[pos] = (int32_t)i;
     }
 }
 
@@ -261,25 +257,37 @@ template <> struct KRow<uint16_t> {
     }
 };
 
-// Grid (column strips, chunks of L positions in V's CSR order).  Each lane owns
-// E consecutive columns (one 16-byte load per row); a wave covers 64 E columns
-// and the workgroup 256 E columns of every row it visits.  A chunk may span
-// several clusters: the running sums are flushed to the partial-buffer slot
-// (chunk + cluster) whenever the cluster changes; the slot is unique per
+// One work item = (column strip, chunk of L positions in V's CSR order).  Each
+// lane owns E consecutive columns (one 16-byte load per row); a wave covers
+// 64 E columns and the workgroup 256 E columns of every row it visits.  A chunk
+// may span several clusters: the running sums are flushed to the partial-buffer
+// slot (chunk + cluster) whenever the cluster changes; the slot is unique per
 // (chunk, cluster) pair.
-template <typename T, bool VEC>
-__global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(
-    const T *__restrict__ K, int64_t ldk, int64_t n, int32_t k,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ offsets,
-    const int32_t *__restrict__ labels, int64_t L, float *__restrict__ P, int64_t ldp,
-    float *__restrict__ Zp, int64_t nws, const int32_t *err) {
+template <typename T, bool VEC, bool MULTI>
+__global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(InstSet s,
+                                                                const int32_t *labels_all) {
     constexpr int E = KRow<T>::E;
-    if (*err != 0) return;
+    int32_t b;
+    int64_t item;
+    const Inst in = locate<MULTI>(s, s.item_start, blockIdx.x, b, item);
+    if (inactive(s, b)) return;
+    if (*in.err != 0) return;
+    const int64_t n = in.n;
+    const int32_t k = in.k;
+    const int64_t L = in.L;
+    const T *__restrict__ K = static_cast<const T *>(in.K);
+    const int64_t ldk = in.ldk;
+    const int32_t *__restrict__ perm = in.perm;
+    const int32_t *__restrict__ offsets = in.offsets;
+    const int32_t *__restrict__ labels = labels_all + in.lab_off;
+    const int64_t nws = in.nws;
+    const int64_t strip = (uint32_t)item % (uint32_t)in.nstrip;
+    const int64_t q = (uint32_t)item / (uint32_t)in.nstrip;
+
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int64_t wave_strip = (int64_t)blockIdx.x * (kSweepThreads / kWave) + (tid >> 6);
+    const int64_t wave_strip = strip * (kSweepThreads / kWave) + (tid >> 6);
     const int64_t col = wave_strip * (kWave * E) + (int64_t)lane * E;
-    const int64_t q = blockIdx.y;
     const int64_t p_begin = q * L;
     const int64_t p_end = min(n, p_begin + L);
 
@@ -301,9 +309,9 @@ __global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(
     while (p < p_end) {
         while (offsets[c + 1] <= p) ++c;  // skip empty clusters
         const int64_t seg_end = min(p_end, (int64_t)offsets[c + 1]);
-        float s[E], e[E];
+        float sum[E], e[E];
 #pragma unroll
-        for (int u = 0; u < E; ++u) s[u] = e[u] = 0.f;
+        for (int u = 0; u < E; ++u) sum[u] = e[u] = 0.f;
         for (; p + 8 <= seg_end; p += 8) {
             float v[8][E];
 #pragma unroll
@@ -316,8 +324,8 @@ __global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(
                 const float blk = ((v[0][u] + v[1][u]) + (v[2][u] + v[3][u])) +
                                   ((v[4][u] + v[5][u]) + (v[6][u] + v[7][u]));
                 float t, er;
-                two_sum(s[u], blk, t, er);
-                s[u] = t;
+                two_sum(sum[u], blk, t, er);
+                sum[u] = t;
                 e[u] += er;
             }
         }
@@ -335,17 +343,17 @@ __global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(
 #pragma unroll
             for (int u = 0; u < E; ++u) {
                 float t, er;
-                two_sum(s[u], blk[u], t, er);
-                s[u] = t;
+                two_sum(sum[u], blk[u], t, er);
+                sum[u] = t;
                 e[u] += er;
             }
         }
         float tot[E];
 #pragma unroll
-        for (int u = 0; u < E; ++u) tot[u] = s[u] + e[u];
+        for (int u = 0; u < E; ++u) tot[u] = sum[u] + e[u];
         const int64_t slot = q + c;
         if (col < n) {
-            float *dst = P + slot * ldp + col;
+            float *dst = in.P + slot * in.ldp + col;
             if (col + E - 1 < n) {
 #pragma unroll
                 for (int u = 0; u < E; u += 4) {
@@ -363,38 +371,39 @@ __global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(
         for (int u = 0; u < E; ++u)
             if (own[u] == c) z += tot[u];
         z = wave_sum(z);
-        if (lane == 0 && wave_strip < nws) Zp[slot * nws + wave_strip] = z;
+        if (lane == 0 && wave_strip < nws) in.Zp[slot * nws + wave_strip] = z;
     }
 }
 
 // ---------------------------------------------------------------- 3. centroid norms
 
-// One workgroup per cluster: ||c_c||^2 = (1/|c|^2) sum_{i in c} S_ic, summing
-// the z partials of the cluster's segments in a fixed order.
-__global__ __launch_bounds__(256) void centroid_norms(const float *Zp, int64_t nws,
-                                                     const int32_t *offsets, int64_t L,
-                                                     int32_t k, float *ctilde,
-                                                     float *ctilde_out, const int32_t *err) {
+// One workgroup per (problem, cluster): ||c_c||^2 = (1/|c|^2) sum_{i in c} S_ic,
+// summing the z partials of the cluster's segments in a fixed order.
+template <int E, bool MULTI>
+__global__ __launch_bounds__(256) void centroid_norms(InstSet s) {
     __shared__ float ss[256], sc[256];
-    if (*err != 0) return;
-    const int c = blockIdx.x;
-    const int64_t a = offsets[c], b = offsets[c + 1];
-    const int64_t cnt = b - a;
-    float s = 0.f, comp = 0.f;
+    int32_t b;
+    int64_t c;
+    const Inst in = locate<MULTI>(s, s.cl_start, blockIdx.x, b, c);
+    if (inactive(s, b)) return;
+    if (*in.err != 0) return;
+    const int64_t nws = in.nws;
+    const int64_t a = in.offsets[c], e = in.offsets[c + 1];
+    const int64_t cnt = e - a;
+    float sum = 0.f, comp = 0.f;
     if (cnt > 0) {
-        const int64_t q0 = a / L, q1 = (b - 1) / L;
-        const int64_t per = nws;
-        const int64_t total = (q1 - q0 + 1) * per;
+        const int64_t q0 = a / in.L, q1 = (e - 1) / in.L;
+        const int64_t total = (q1 - q0 + 1) * nws;
         for (int64_t t = threadIdx.x; t < total; t += 256) {
-            const int64_t q = q0 + t / per;
-            const int64_t w = t % per;
+            const int64_t q = q0 + t / nws;
+            const int64_t w = t % nws;
             float u, er;
-            two_sum(s, Zp[(q + c) * nws + w], u, er);
-            s = u;
+            two_sum(sum, in.Zp[(q + c) * nws + w], u, er);
+            sum = u;
             comp += er;
         }
     }
-    ss[threadIdx.x] = s;
+    ss[threadIdx.x] = sum;
     sc[threadIdx.x] = comp;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -412,44 +421,51 @@ __global__ __launch_bounds__(256) void centroid_norms(const float *Zp, int64_t n
             const float fc = (float)cnt;
             v = ((ss[0] + sc[0]) / fc) / fc;
         }
-        ctilde[c] = v;
-        if (ctilde_out) ctilde_out[c] = v;
+        in.ctilde[c] = v;
+        if (in.ctilde_out) in.ctilde_out[c] = v;
     }
 }
 
 // ---------------------------------------------------------------- 4. distances + argmin + histogram
 
-__global__ __launch_bounds__(kPtsPerBlock) void assign_fused(
-    const float *__restrict__ P, int64_t ldp, const int32_t *__restrict__ offsets, int64_t L,
-    const float *__restrict__ ctilde, const float *__restrict__ diagK,
-    const int32_t *__restrict__ labels_in, int64_t n, int32_t k, int32_t empty_policy,
-    int32_t *__restrict__ labels_out, int32_t *counts_out, int64_t *n_changed, double *J_in,
-    double *Jpart, uint32_t *ticket, float *D_out, const int32_t *err) {
-    extern __shared__ int32_t sh[];  // off[k+1], hist[k], then doubles
-    int32_t *off = sh;
-    int32_t *hist = sh + (k + 1);
+template <bool MULTI>
+__global__ __launch_bounds__(kPtsPerBlock) void assign_fused(InstSet s,
+                                                             const int32_t *labels_in_all,
+                                                             int32_t *labels_out_all) {
+    extern __shared__ int32_t sh[];  // off[k+1], hist[k]
     __shared__ double wJ[kPtsPerBlock / kWave];
     __shared__ long long wC[kPtsPerBlock / kWave];
     __shared__ bool last;
+    int32_t b;
+    int64_t lb;
+    const Inst in = locate<MULTI>(s, s.blk_start, blockIdx.x, b, lb);
+    if (inactive(s, b)) return;
+    const int32_t k = in.k;
+    const int64_t L = in.L, ldp = in.ldp;
+    const float *__restrict__ P = in.P;
+    const int32_t *__restrict__ labels_in = labels_in_all + in.lab_off;
+    int32_t *__restrict__ labels_out = labels_out_all + in.lab_off;
+    int32_t *off = sh;
+    int32_t *hist = sh + (k + 1);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    if (*err != 0) {
-        if (blockIdx.x == 0 && tid == 0) {
-            *n_changed = -1;
-            *J_in = __builtin_nan("");
+    if (*in.err != 0) {
+        if (lb == 0 && tid == 0) {
+            *in.n_changed = -1;
+            *in.J_in = __builtin_nan("");
         }
         return;
     }
-    for (int c = tid; c <= k; c += kPtsPerBlock) off[c] = offsets[c];
+    for (int c = tid; c <= k; c += kPtsPerBlock) off[c] = in.offsets[c];
     for (int c = tid; c < k; c += kPtsPerBlock) hist[c] = 0;
     __syncthreads();
 
-    const int64_t i = (int64_t)blockIdx.x * kPtsPerBlock + tid;
-    const bool valid = i < n;
+    const int64_t i = lb * kPtsPerBlock + tid;
+    const bool valid = i < in.n;
     double own_d = 0.0;
     long long changed = 0;
     if (valid) {
-        const float dii = diagK[i];
+        const float dii = in.diag[i];
         const int32_t a_in = labels_in[i];
         float best = __builtin_inff();
         int32_t arg = -1;
@@ -458,19 +474,19 @@ __global__ __launch_bounds__(kPtsPerBlock) void assign_fused(
             const int64_t lo = off[c], hi = off[c + 1];
             float dic;
             if (hi > lo) {
-                float s = 0.f, comp = 0.f;
+                float sum = 0.f, comp = 0.f;
                 for (int64_t q = lo / L; q <= (hi - 1) / L; ++q) {
                     float u, er;
-                    two_sum(s, P[(q + c) * ldp + i], u, er);
-                    s = u;
+                    two_sum(sum, P[(q + c) * ldp + i], u, er);
+                    sum = u;
                     comp += er;
                 }
-                const float e = (s + comp) / (float)(hi - lo);
-                dic = fmaf(-2.0f, e, dii) + ctilde[c];
+                const float e = (sum + comp) / (float)(hi - lo);
+                dic = fmaf(-2.0f, e, dii) + in.ctilde[c];
             } else {
-                dic = (empty_policy == KKM_EMPTY_ZERO_CENTROID) ? dii : __builtin_inff();
+                dic = (in.empty_policy == KKM_EMPTY_ZERO_CENTROID) ? dii : __builtin_inff();
             }
-            if (D_out) D_out[i * k + c] = dic;
+            if (in.D_out) in.D_out[i * k + c] = dic;
             if (c == a_in) own = dic;
             if (dic < best) {
                 best = dic;
@@ -498,60 +514,196 @@ __global__ __launch_bounds__(kPtsPerBlock) void assign_fused(
             bj += wJ[w];
             bc += wC[w];
         }
-        Jpart[blockIdx.x] = bj;
-        if (bc) atomicAdd((unsigned long long *)n_changed, (unsigned long long)bc);
+        in.Jpart[lb] = bj;
+        if (bc) atomicAdd((unsigned long long *)in.n_changed, (unsigned long long)bc);
     }
     for (int c = tid; c < k; c += kPtsPerBlock)
-        if (hist[c]) atomicAdd(&counts_out[c], hist[c]);
+        if (hist[c]) atomicAdd(&in.counts_out[c], hist[c]);
 
-    // the last block to finish sums the block partials of J in block order
+    // the problem's last block to finish sums its block partials of J in order
     __threadfence();
     __syncthreads();
-    if (tid == 0) last = (atomicAdd(ticket, 1u) == gridDim.x - 1);
+    if (tid == 0) last = (atomicAdd(in.ticket, 1u) == (uint32_t)(in.nblk - 1));
     __syncthreads();
     if (!last) return;
     __threadfence();
-    double s = 0.0;
-    for (int64_t b = tid; b < (int64_t)gridDim.x; b += kPtsPerBlock) s += Jpart[b];
-    const double ws = wave_sum(s);
+    double acc = 0.0;
+    for (int64_t t = tid; t < in.nblk; t += kPtsPerBlock) acc += in.Jpart[t];
+    const double ws = wave_sum(acc);
     if (lane == 0) wJ[wave] = ws;
     __syncthreads();
     if (tid == 0) {
-        double t = 0.0;
-        for (int w = 0; w < kPtsPerBlock / kWave; ++w) t += wJ[w];
-        *J_in = t;
+        double tot = 0.0;
+        for (int w = 0; w < kPtsPerBlock / kWave; ++w) tot += wJ[w];
+        *in.J_in = tot;
     }
+}
+
+// Geometry shared by the workspace sizing and the kernels.
+int64_t chunk_rows(int64_t n) {
+    // the largest power of two in [64, 4096] that still gives about 8192 sweep
+    // workgroups of 1024 FP32 columns (the partial sums cost slots * n floats)
+    const int64_t nstrip = (n + 1023) / 1024;
+    int64_t L = 4096;
+    while (L > 64 && ((n + L - 1) / L) * nstrip < 8192) L >>= 1;
+    return L;
 }
 
 }  // namespace
 
-// V in CSR form from labels in [0, k): cluster sizes, row pointers (offsets)
-// and column indices (perm, stable).  blk_hist holds k * ceil(n/256) ints and
-// blk_bad ceil(n/256) ints; *err ends up non-zero when a label is out of range
-// (perm is then incomplete).  counts_out[k], *n_changed and *ticket are
-// cleared on the way, for a following assignment kernel.
+InstGeom inst_geometry(int64_t n, int32_t k, int64_t L) {
+    InstGeom g;
+    g.n = n;
+    g.k = k;
+    g.L = (L > 0) ? L : chunk_rows(n);
+    g.nblk = (n + kPtsPerBlock - 1) / kPtsPerBlock;
+    g.nchunk = (n + g.L - 1) / g.L;
+    g.slots = g.nchunk + k;
+    g.ldp = (n + 63) & ~int64_t(63);
+    g.nws_max = (n + kWave * 4 - 1) / (kWave * 4);  // FP32 K: the most wave strips
+    return g;
+}
+
+size_t inst_workspace_bytes(const InstGeom &g) {
+    size_t bytes = 0;
+    inst_carve(nullptr, g, nullptr, &bytes);
+    return bytes;
+}
+
+void inst_carve(void *base, const InstGeom &g, Inst *in, size_t *bytes) {
+    Carver c(base);
+    int32_t *perm = c.take<int32_t>((size_t)g.n);
+    int32_t *offsets = c.take<int32_t>((size_t)g.k + 1);
+    int32_t *counts = c.take<int32_t>((size_t)g.k);
+    int32_t *blk_hist = c.take<int32_t>((size_t)g.k * (size_t)g.nblk);
+    int32_t *blk_bad = c.take<int32_t>((size_t)g.nblk);
+    int32_t *err = c.take<int32_t>(1);
+    float *P = c.take<float>((size_t)g.slots * (size_t)g.ldp);
+    float *Zp = c.take<float>((size_t)g.slots * (size_t)g.nws_max);
+    float *ctilde = c.take<float>((size_t)g.k);
+    double *Jpart = c.take<double>((size_t)g.nblk);
+    uint32_t *ticket = c.take<uint32_t>(1);
+    if (bytes) *bytes = c.bytes();
+    if (!in) return;
+    in->n = g.n;
+    in->k = g.k;
+    in->L = g.L;
+    in->nblk = g.nblk;
+    in->ldp = g.ldp;
+    in->perm = perm;
+    in->offsets = offsets;
+    in->counts = counts;
+    in->blk_hist = blk_hist;
+    in->blk_bad = blk_bad;
+    in->err = err;
+    in->P = P;
+    in->Zp = Zp;
+    in->ctilde = ctilde;
+    in->Jpart = Jpart;
+    in->ticket = ticket;
+}
+
+int64_t inst_sweep_items(const InstGeom &g, int32_t k_store) {
+    const int64_t cols = (int64_t)kSweepThreads * ((k_store == KKM_BF16) ? 8 : 4);
+    return ((g.n + cols - 1) / cols) * g.nchunk;
+}
+
+void inst_set_store(Inst *in, int32_t k_store) {
+    const int64_t E = (k_store == KKM_BF16) ? 8 : 4;
+    in->nstrip = (in->n + kSweepThreads * E - 1) / (kSweepThreads * E);
+    in->nws = (in->n + kWave * E - 1) / (kWave * E);
+}
+
+namespace {
+
+template <bool MULTI>
+kkm_status step_launch_t(const InstSet &s, int64_t total_blocks, int64_t total_clusters,
+                         int64_t total_items, int32_t max_k, int32_t k_store, bool vec,
+                         const int32_t *labels_in, int32_t *labels_out, hipStream_t stream) {
+    const dim3 pb(kPtsPerBlock);
+    const TimedSpan whole = timing_begin(TK_ITERATE, stream);
+    hipLaunchKernelGGL(v_block_hist<MULTI>, dim3((unsigned)total_blocks), pb,
+                       (size_t)(max_k + 1) * sizeof(int32_t), stream, s, labels_in);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(v_cluster_scan<MULTI>, dim3((unsigned)total_clusters), dim3(256), 0, stream, s);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(v_scatter<MULTI>, dim3((unsigned)total_blocks), pb,
+                       (size_t)(max_k + 1 + 4 * max_k) * sizeof(int32_t), stream, s, labels_in);
+    KKM_HIP(hipGetLastError());
+    const dim3 sg((unsigned)total_items), sb(kSweepThreads);
+    const TimedSpan span = timing_begin(TK_SWEEP, stream);
+    if (k_store == KKM_F32) {
+        if (vec)
+            hipLaunchKernelGGL((spmm_row_sweep<float, true, MULTI>), sg, sb, 0, stream, s, labels_in);
+        else
+            hipLaunchKernelGGL((spmm_row_sweep<float, false, MULTI>), sg, sb, 0, stream, s, labels_in);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((spmm_row_sweep<uint16_t, true, MULTI>), sg, sb, 0, stream, s, labels_in);
+        else
+            hipLaunchKernelGGL((spmm_row_sweep<uint16_t, false, MULTI>), sg, sb, 0, stream, s, labels_in);
+    }
+    KKM_HIP(hipGetLastError());
+    timing_end(span, stream);
+    if (k_store == KKM_F32)
+        hipLaunchKernelGGL((centroid_norms<4, MULTI>), dim3((unsigned)total_clusters), dim3(256), 0, stream, s);
+    else
+        hipLaunchKernelGGL((centroid_norms<8, MULTI>), dim3((unsigned)total_clusters), dim3(256), 0, stream, s);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(assign_fused<MULTI>, dim3((unsigned)total_blocks), pb,
+                       (size_t)(2 * max_k + 1) * sizeof(int32_t), stream, s, labels_in, labels_out);
+    KKM_HIP(hipGetLastError());
+    timing_end(whole, stream);
+    return KKM_OK;
+}
+
+}  // namespace
+
+kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clusters,
+                       int64_t total_items, int32_t max_k, int32_t k_store, bool vec,
+                       const int32_t *labels_in, int32_t *labels_out, hipStream_t stream) {
+    if (s.table)
+        return step_launch_t<true>(s, total_blocks, total_clusters, total_items, max_k, k_store,
+                                   vec, labels_in, labels_out, stream);
+    return step_launch_t<false>(s, total_blocks, total_clusters, total_items, max_k, k_store, vec,
+                                labels_in, labels_out, stream);
+}
+
+// V in CSR form for one problem (used by the feature-space Lloyd iterations):
+// the first three kernels of a step on a set of one.
 kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
                       int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,
                       int32_t *offsets, int32_t *counts_out, int64_t *n_changed,
                       uint32_t *ticket, hipStream_t stream) {
-    const int64_t nblk = (n + kPtsPerBlock - 1) / kPtsPerBlock;
-    hipLaunchKernelGGL(v_block_hist, dim3((unsigned)nblk), dim3(kPtsPerBlock),
-                       (k + 1) * sizeof(int32_t), stream, labels, n, k, nblk, blk_hist, blk_bad);
+    InstSet s{};
+    s.count = 1;
+    Inst &in = s.one;
+    in.n = n;
+    in.k = k;
+    in.nblk = (n + kPtsPerBlock - 1) / kPtsPerBlock;
+    in.blk_hist = blk_hist;
+    in.blk_bad = blk_bad;
+    in.err = err;
+    in.counts = counts;
+    in.perm = perm;
+    in.offsets = offsets;
+    in.counts_out = counts_out;
+    in.n_changed = n_changed;
+    in.ticket = ticket;
+    const dim3 pb(kPtsPerBlock);
+    hipLaunchKernelGGL(v_block_hist<false>, dim3((unsigned)in.nblk), pb, (size_t)(k + 1) * sizeof(int32_t),
+                       stream, s, labels);
     KKM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(v_cluster_scan, dim3((unsigned)k), dim3(256), 0, stream, blk_hist, nblk,
-                       counts, blk_bad, err);
+    hipLaunchKernelGGL(v_cluster_scan<false>, dim3((unsigned)k), dim3(256), 0, stream, s);
     KKM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(v_scatter, dim3((unsigned)nblk), dim3(kPtsPerBlock),
-                       (size_t)(k + 1 + 4 * k) * sizeof(int32_t), stream, labels, n, k, nblk,
-                       blk_hist, counts, err, perm, offsets, counts_out, n_changed, ticket);
+    hipLaunchKernelGGL(v_scatter<false>, dim3((unsigned)in.nblk), pb,
+                       (size_t)(k + 1 + 4 * k) * sizeof(int32_t), stream, s, labels);
     KKM_HIP(hipGetLastError());
     return KKM_OK;
 }
 
 size_t iterate_workspace_bytes(int64_t n, int32_t k) {
-    size_t bytes = 0;
-    carve(nullptr, make_geometry(n, k), &bytes);
-    return bytes;
+    return inst_workspace_bytes(inst_geometry(n, k, 0));
 }
 
 kkm_status iterate_launch(const void *K, int32_t k_store, int64_t ldk, const float *diagK,
@@ -559,57 +711,32 @@ kkm_status iterate_launch(const void *K, int32_t k_store, int64_t ldk, const flo
                           int32_t *labels_out, int32_t *counts_out, int64_t *n_changed,
                           double *J_in, float *D_out, float *ctilde_out, void *ws,
                           size_t ws_bytes, hipStream_t stream) {
-    const Geometry g = make_geometry(n, k);
+    const InstGeom g = inst_geometry(n, k, 0);
     size_t need = 0;
-    IterWs w = carve(ws, g, &need);
+    inst_carve(nullptr, g, nullptr, &need);
     if (ws == nullptr || ws_bytes < need) {
         set_error("kkm_iterate: workspace of %zu bytes is smaller than %zu", ws_bytes, need);
         return KKM_ERR_NOMEM;
     }
-    const unsigned nblk = (unsigned)g.nblk;
-    const TimedSpan whole = timing_begin(TK_ITERATE, stream);
-    KKM_TRY(vcsr_build(labels_in, n, k, w.blk_hist, w.blk_bad, w.err, w.counts, w.perm,
-                       w.offsets, counts_out, n_changed, w.ticket, stream));
-    // one 16-byte load per lane and row: 4 FP32 or 8 BF16 columns
+    InstSet s{};
+    s.count = 1;
+    Inst &in = s.one;
+    inst_carve(ws, g, &in, nullptr);
+    in.K = K;
+    in.ldk = ldk;
+    in.diag = diagK;
+    in.lab_off = 0;
+    in.empty_policy = empty_policy;
+    in.counts_out = counts_out;
+    in.n_changed = n_changed;
+    in.J_in = J_in;
+    in.D_out = D_out;
+    in.ctilde_out = ctilde_out;
+    inst_set_store(&in, k_store);
     const int E = (k_store == KKM_BF16) ? 8 : 4;
-    const int64_t cols_per_wg = (int64_t)kSweepThreads * E;
-    const int64_t nstrip = (n + cols_per_wg - 1) / cols_per_wg;
-    const int64_t nws = (n + kWave * E - 1) / (kWave * E);
     const bool vec = ((ldk % E) == 0) && ((reinterpret_cast<uintptr_t>(K) & 15) == 0);
-    const dim3 sgrid((unsigned)nstrip, (unsigned)g.nchunk);
-    const dim3 sblk(kSweepThreads);
-    const TimedSpan span = timing_begin(TK_SWEEP, stream);
-    if (k_store == KKM_F32) {
-        const float *Kf = static_cast<const float *>(K);
-        if (vec)
-            hipLaunchKernelGGL((spmm_row_sweep<float, true>), sgrid, sblk, 0, stream, Kf, ldk, n,
-                               k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, nws, w.err);
-        else
-            hipLaunchKernelGGL((spmm_row_sweep<float, false>), sgrid, sblk, 0, stream, Kf, ldk, n,
-                               k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, nws, w.err);
-    } else {
-        const uint16_t *Kh = static_cast<const uint16_t *>(K);
-        if (vec)
-            hipLaunchKernelGGL((spmm_row_sweep<uint16_t, true>), sgrid, sblk, 0, stream, Kh, ldk,
-                               n, k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, nws,
-                               w.err);
-        else
-            hipLaunchKernelGGL((spmm_row_sweep<uint16_t, false>), sgrid, sblk, 0, stream, Kh, ldk,
-                               n, k, w.perm, w.offsets, labels_in, g.L, w.P, g.ldp, w.Zp, nws,
-                               w.err);
-    }
-    KKM_HIP(hipGetLastError());
-    timing_end(span, stream);
-    hipLaunchKernelGGL(centroid_norms, dim3((unsigned)k), dim3(256), 0, stream, w.Zp, nws,
-                       w.offsets, g.L, k, w.ctilde, ctilde_out, w.err);
-    KKM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(assign_fused, dim3(nblk), dim3(kPtsPerBlock),
-                       (size_t)(2 * k + 1) * sizeof(int32_t), stream, w.P, g.ldp, w.offsets,
-                       g.L, w.ctilde, diagK, labels_in, n, k, empty_policy, labels_out,
-                       counts_out, n_changed, J_in, w.Jpart, w.ticket, D_out, w.err);
-    KKM_HIP(hipGetLastError());
-    timing_end(whole, stream);
-    return KKM_OK;
+    return step_launch(s, g.nblk, k, inst_sweep_items(g, k_store), k, k_store, vec, labels_in,
+                       labels_out, stream);
 }
 
 }  // namespace kkm
