@@ -173,6 +173,66 @@ kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t
                       double *times_ms, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Batched form: many independent clustering problems of uneven sizes, each
+ * the computation of kkm_fit_ex (Algorithm 2 of the paper run once per
+ * problem), sharing every launch.  One persistent Gram launch takes 128 x 128
+ * tiles of all problems from a device queue, problems with the costliest
+ * tiles first; then each iteration is one set of launches over the problems
+ * still running, replayed from a captured HIP graph while a device-side
+ * predicate retires converged problems.
+ */
+
+/* One problem of a batch (host struct; X is a device pointer). */
+typedef struct {
+    const float *X;      /* [n, ldx] float32 points, row-major              */
+    int64_t n, d, ldx;   /* n >= 1, d >= 1, ldx >= d                        */
+    int32_t k;           /* 1 <= k <= min(n, KKM_MAX_K)                     */
+    int32_t kernel_type; /* kernel function, as kkm_gram                    */
+    double gamma, coef0;
+    int32_t degree;
+    int32_t chunk_rows;  /* rows of K per sweep workgroup, in [1, 2^20];
+                            0 = the single-problem default (results then
+                            match kkm_fit_ex bit for bit)                   */
+} kkm_instance;
+
+/*
+ * kkm_fit_batched_workspace_bytes — device workspace that kkm_fit_batched
+ * needs for these problems: every K (n x roundup(n, 64) elements of k_store,
+ * kept for the whole run), the rounded rows of the product, the per-problem
+ * step buffers and the instance tables.  0 on invalid arguments.
+ */
+size_t kkm_fit_batched_workspace_bytes(const kkm_instance *inst, int32_t count,
+                                       int32_t gram_prec, int32_t k_store);
+
+/*
+ * kkm_fit_batched — kkm_fit_ex for each of `count` problems.
+ *
+ *   inst          host kkm_instance [count].
+ *   gram_prec, k_store, empty_policy   as kkm_fit_ex, for every problem.
+ *   labels0       int32 [sum n]: the initial labels of problem 0, then of
+ *                 problem 1, ... (problem b starts at n_0 + ... + n_{b-1}).
+ *   max_iter, check_convergence   as kkm_fit_ex, for every problem.
+ *   use_graph     1: the iteration is captured once into a HIP graph (one
+ *                 per label-buffer parity) and replayed; 0: launched
+ *                 directly.  The results are identical.
+ *   labels_out    int32 [sum n], same layout as labels0.
+ *   objective     host double [count]: J(labels_out) of each problem.
+ *   iters         host int32 [count]: steps run per problem (as kkm_fit_ex).
+ *   times_ms      host double [3], nullable: {Gram with its prologue, all
+ *                 steps, final objective pass} on the stream.
+ *   ws, ws_bytes  workspace of kkm_fit_batched_workspace_bytes bytes, or
+ *                 NULL to let the call allocate (and free) it.
+ * Synchronises the stream before returning.  KKM_ERR_LABEL names the first
+ * problem whose labels0 holds a label outside [0, k); KKM_ERR_NONFINITE is
+ * returned when any problem's diag(K) is not finite.
+ */
+kkm_status kkm_fit_batched(const kkm_instance *inst, int32_t count, int32_t gram_prec,
+                           int32_t k_store, int32_t empty_policy, const int32_t *labels0,
+                           int32_t max_iter, int32_t check_convergence, int32_t use_graph,
+                           int32_t *labels_out, double *objective, int32_t *iters,
+                           double *times_ms, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned warm start.  The paper draws the initial labels at random (Sec.
  * 3.4); these entry points produce a better start: a small network
  * phi_theta: R^d -> R^h1 -> R^h2 -> R^out (GELU after the first two layers,

@@ -28,6 +28,7 @@ EXPORTS = ("kkm_gram", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_w
            "kkm_mlp_adam", "kkm_mlp_train", "kkm_feature_lloyd", "kkm_feature_lloyd_workspace_bytes",
            "kkm_feature_kmeanspp", "kkm_feature_kmeanspp_workspace_bytes",
            "kkm_mlp_train_fresh", "kkm_mlp_train_fresh_workspace_bytes",
+           "kkm_fit_batched", "kkm_fit_batched_workspace_bytes",
            "kkm_timing_enable", "kkm_timing_read", "kkm_last_error")
 
 
@@ -39,6 +40,13 @@ class KKMError(RuntimeError):
 
 _lib = None
 _vp, _i64, _i32, _d, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+
+
+class KkmInstance(ctypes.Structure):
+    """The C struct kkm_instance (one problem of a batch)."""
+    _fields_ = [("X", _vp), ("n", _i64), ("d", _i64), ("ldx", _i64), ("k", _i32),
+                ("kernel_type", _i32), ("gamma", _d), ("coef0", _d), ("degree", _i32),
+                ("chunk_rows", _i32)]
 
 
 def lib():
@@ -100,6 +108,11 @@ def lib():
         L.kkm_feature_kmeanspp_workspace_bytes.argtypes = [_i64, _i64, _i32]
         L.kkm_feature_kmeanspp.restype = ctypes.c_int
         L.kkm_feature_kmeanspp.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.kkm_fit_batched_workspace_bytes.restype = _sz
+        L.kkm_fit_batched_workspace_bytes.argtypes = [ctypes.POINTER(KkmInstance), _i32, _i32, _i32]
+        L.kkm_fit_batched.restype = ctypes.c_int
+        L.kkm_fit_batched.argtypes = [ctypes.POINTER(KkmInstance), _i32, _i32, _i32, _i32, _vp,
+                                      _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
         L.kkm_timing_enable.restype = ctypes.c_int
         L.kkm_timing_enable.argtypes = [_i32]
         L.kkm_timing_read.restype = ctypes.c_int
@@ -262,6 +275,57 @@ def kkm_fit_ex(X, k, labels0, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram
     t = int(it.value)
     return dict(labels=labels_out, objective=J.value, iters=t, J_trace=Jt[:t + 1],
                 changed_trace=Ct[:t], times_ms=tm)
+
+
+def _instances(problems):
+    arr = (KkmInstance * len(problems))()
+    for b, p in enumerate(problems):
+        X = p["X"]
+        _dev(X, torch.float32, "problems[%d].X" % b, 2)
+        n, d, ldx = _rows(X, "problems[%d].X" % b)
+        arr[b] = KkmInstance(X.data_ptr(), n, d, ldx, int(p["k"]), int(p.get("kernel", GAUSS)),
+                             float(p.get("gamma", 1.0)), float(p.get("coef0", 0.0)),
+                             int(p.get("degree", 1)), int(p.get("chunk_rows", 0)))
+    return arr
+
+
+def kkm_fit_batched_workspace_bytes(problems, gram_prec=F32, k_store=F32) -> int:
+    arr = _instances(problems)
+    return int(lib().kkm_fit_batched_workspace_bytes(arr, len(problems), gram_prec, k_store))
+
+
+def kkm_fit_batched(problems, labels0, gram_prec=F32, k_store=F32, empty_policy=EMPTY_INF,
+                    max_iter=30, check_convergence=True, use_graph=True, labels_out=None,
+                    ws=None):
+    """kkm_fit_ex for many problems in shared launches.
+
+    problems: list of dicts with X (device float32 [n, d], row stride allowed),
+    k, kernel, gamma, coef0, degree and optionally chunk_rows.  labels0: int32
+    device vector of sum(n) labels, problem after problem.  Returns a dict with
+    labels (same layout), objective (float64 [count]), iters (int32 [count])
+    and times_ms (Gram, steps, final pass)."""
+    import numpy as np
+
+    arr = _instances(problems)
+    count = len(problems)
+    total = sum(int(a.n) for a in arr)
+    _dev(labels0, torch.int32, "labels0", 1)
+    if labels0.shape[0] != total:
+        raise ValueError("labels0 must hold sum(n) = %d labels" % total)
+    if labels_out is None:
+        labels_out = torch.empty(total, dtype=torch.int32, device=labels0.device)
+    ws_bytes = 0
+    if ws is not None:
+        _dev(ws, torch.uint8, "ws", 1)
+        ws_bytes = ws.numel()
+    obj = np.zeros(count, dtype=np.float64)
+    its = np.zeros(count, dtype=np.int32)
+    tm = np.zeros(3, dtype=np.float64)
+    _check(lib().kkm_fit_batched(arr, count, gram_prec, k_store, empty_policy, _ptr(labels0),
+                                 max_iter, int(bool(check_convergence)), int(bool(use_graph)),
+                                 _ptr(labels_out), obj.ctypes.data_as(_vp), its.ctypes.data_as(_vp),
+                                 tm.ctypes.data_as(_vp), _ptr(ws), ws_bytes, _stream()))
+    return dict(labels=labels_out, objective=obj, iters=its, times_ms=tm)
 
 
 def kkm_timing_enable(on: bool = True):

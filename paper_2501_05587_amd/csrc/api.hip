@@ -58,6 +58,10 @@ TimedSpan timing_begin(int cls, hipStream_t stream) {
     TimedSpan sp;
     std::lock_guard<std::mutex> g(g_timing_mu);
     if (!timing().on) return sp;
+    // launches being captured into a graph run later: they are not timed
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+        return sp;
     if (hipEventCreate(&sp.start) != hipSuccess || hipEventCreate(&sp.stop) != hipSuccess) return sp;
     sp.cls = cls;
     (void)hipEventRecord(sp.start, stream);
@@ -70,8 +74,6 @@ void timing_end(const TimedSpan &sp, hipStream_t stream) {
     std::lock_guard<std::mutex> g(g_timing_mu);
     timing().spans.push_back(sp);
 }
-
-namespace {
 
 kkm_status check_kernel(int32_t kernel_type, double gamma, double coef0, int32_t degree) {
     if (kernel_type != KKM_LINEAR && kernel_type != KKM_POLY && kernel_type != KKM_GAUSS) {
@@ -104,15 +106,30 @@ kkm_status check_dtypes(int32_t gram_prec, int32_t k_store) {
 
 size_t elem_bytes(int32_t k_store) { return k_store == KKM_BF16 ? 2 : 4; }
 
-__global__ void flag_nonfinite(const float *v, int64_t n, int32_t *flag) {
+__global__ void flag_nonfinite_kernel(const float *v, int64_t n, int32_t *flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && !isfinite(v[i])) atomicOr(flag, 1);
 }
 
-__global__ void fill_i32(int32_t *p, int64_t n, int32_t v) {
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
+
+void flag_nonfinite(const float *v, int64_t n, int32_t *flag, hipStream_t stream) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(1), 0, stream, flag, (int64_t)1, 0);
+    if (n > 0)
+        hipLaunchKernelGGL(flag_nonfinite_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           stream, v, n, flag);
+}
+
+void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream) {
+    if (n > 0)
+        hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                           p, n, v);
+}
+
+namespace {
 
 // Device buffers owned by one kkm_fit call.
 struct FitBuffers {
@@ -314,9 +331,7 @@ extern "C" kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t l
     KKM_HIP(hipEventRecord(ev[0], s));
     KKM_TRY(gram_launch(X, n, d, ldx, kernel_type, gamma, coef0, degree, gram_prec, k_store, K,
                         ldk, diag, gram_ws, gws, s));
-    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(1), 0, s, flag, (int64_t)1, 0);
-    hipLaunchKernelGGL(flag_nonfinite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, diag,
-                       n, flag);
+    flag_nonfinite(diag, n, flag, s);
     KKM_HIP(hipGetLastError());
     KKM_HIP(hipEventRecord(ev[1], s));
     KKM_HIP(hipMemcpyAsync(lab[0], labels0, (size_t)n * sizeof(int32_t),

@@ -31,109 +31,17 @@ using namespace gt;
 
 // ---------------------------------------------------------------- FP32 product
 
-constexpr int GK = 32;        // k-slab staged in LDS per step (floats)
-constexpr int GLD = GK + 4;   // padded LDS row stride in floats (conflict-free b128 reads)
-
 struct F32Args {
-    const float *X;
-    int64_t d, ldx;
+    F32Tile t;
     int64_t ntiles, per_xcd;
-    int vec_x;
-    Epi e;
 };
-
-__device__ __forceinline__ f32x4 load_row4(const F32Args &a, int64_t row, int64_t col) {
-    f32x4 v = {0.f, 0.f, 0.f, 0.f};
-    if (row < a.e.n) {
-        const float *src = a.X + row * a.ldx + col;
-        if (a.vec_x && col + 3 < a.d) {
-            v = *reinterpret_cast<const f32x4 *>(src);
-        } else {
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (col + u < a.d) v[u] = src[u];
-        }
-    }
-    return v;
-}
 
 template <typename OUT>
 __global__ __launch_bounds__(GTHREADS, 2) void gram_f32_mfma(F32Args a) {
-    __shared__ __attribute__((aligned(16))) float lds[2][2][GM * GLD];
+    __shared__ __attribute__((aligned(16))) F32Lds lds;
     int64_t bi, bj;
     if (!tile_of_block(a.ntiles, a.per_xcd, bi, bj)) return;
-    const int64_t m0 = bi * GM, n0 = bj * GM;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int ld_row = tid >> 3;        // 8 threads per 32-float row slice
-    const int ld_col = (tid & 7) * 4;
-
-    f32x4 ra[4], rb[4];
-    auto gload = [&](int64_t k0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            ra[u] = load_row4(a, m0 + ld_row + 32 * u, k0 + ld_col);
-            rb[u] = load_row4(a, n0 + ld_row + 32 * u, k0 + ld_col);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            *reinterpret_cast<f32x4 *>(&lds[buf][0][(ld_row + 32 * u) * GLD + ld_col]) = ra[u];
-            *reinterpret_cast<f32x4 *>(&lds[buf][1][(ld_row + 32 * u) * GLD + ld_col]) = rb[u];
-        }
-    };
-
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-    const int64_t nk = (a.d + GK - 1) / GK;
-    gload(0);
-    sstore(0);
-    __syncthreads();
-
-    // The 32x32x2 MFMA takes A[i][kk] from lane (kk*32 + i) and B[kk][j] from
-    // lane (kk*32 + j).  Within a slab the k index is permuted the same way for
-    // both operands (lane half h covers k = 16h .. 16h+15 across 16 MFMAs), so
-    // each lane fetches 16 consecutive floats with four b128 LDS reads.
-    const int half = lane >> 5;
-    const int l32 = lane & 31;
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * GK);
-        const float *As = lds[buf][0];
-        const float *Bs = lds[buf][1];
-        f32x4 av[2][4], bv[2][4];
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-            const float *pa = As + (wr * 64 + mi * 32 + l32) * GLD + half * 16;
-            const float *pb = Bs + (wc * 64 + mi * 32 + l32) * GLD + half * 16;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                av[mi][q] = *reinterpret_cast<const f32x4 *>(pa + 4 * q);
-                bv[mi][q] = *reinterpret_cast<const f32x4 *>(pb + 4 * q);
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < 16; ++s)
-#pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < 2; ++ni)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                        av[mi][s >> 2][s & 3], bv[ni][s >> 2][s & 3], acc[mi][ni], 0, 0, 0);
-        if (kt + 1 < nk) sstore(buf ^ 1);
-        __syncthreads();
-    }
-    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane);
+    f32_tile<OUT>(a.t, bi, bj, lds);
 }
 
 // ---------------------------------------------------------------- BF16 / FP8 product
@@ -155,11 +63,7 @@ __global__ __launch_bounds__(256) void row_sqnorms(const float *X, int64_t n, in
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
-    const float *x = X + row * ldx;
-    float s = 0.f;
-    for (int64_t l = lane; l < d; l += kWave) s = fmaf(x[l], x[l], s);
-    s = wave_sum(s);
-    if (lane == 0) nrm[row] = s;
+    sqnorm_row(X + row * ldx, d, nrm + row, lane);
 }
 
 // One wave per row: rounds the row and records its squared norm (and scale).
@@ -173,11 +77,6 @@ __global__ __launch_bounds__(256) void quantize_rows(const float *X, int64_t n, 
     const int64_t eb = (PREC == KKM_BF16) ? 2 : 1;
     quantize_row<PREC>(X + row * ldx, d, dpad, Xq + row * dpad * eb, nrm + row, scale + row,
                        threadIdx.x & 63);
-}
-
-int64_t padded_d(int64_t d, int32_t gram_prec) {
-    const int64_t per = (gram_prec == KKM_BF16) ? 64 : 128;
-    return (d + per - 1) / per * per;
 }
 
 }  // namespace
@@ -234,13 +133,13 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
             KKM_HIP(hipGetLastError());
         }
         F32Args a;
-        a.X = X;
-        a.d = d;
-        a.ldx = ldx;
+        a.t.X = X;
+        a.t.d = d;
+        a.t.ldx = ldx;
+        a.t.vec_x = ((ldx % 4) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+        a.t.e = e;
         a.ntiles = ntiles;
         a.per_xcd = per_xcd;
-        a.vec_x = ((ldx % 4) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
-        a.e = e;
         const TimedSpan span = timing_begin(TK_GRAM, stream);
         if (k_store == KKM_F32)
             hipLaunchKernelGGL(gram_f32_mfma<float>, dim3((unsigned)grid), dim3(GTHREADS), 0,

@@ -1,7 +1,8 @@
 // Device-side pieces of the kernel-matrix product shared by the single- and
-// many-instance Gram kernels: the 128 x 128 tile of the BF16 / FP8 MFMA
-// product with its fused epilogue (kappa, diagonal, mirrored stores), and the
-// rounding of a row to the product's input type.  Internal to the library.
+// many-instance Gram kernels: the 128 x 128 tile of the FP32 and of the
+// BF16 / FP8 MFMA product with its fused epilogue (kappa, diagonal, mirrored
+// stores), and the row prologues (squared norm; rounding to the product's
+// input type).  Internal to the library.
 #pragma once
 
 #include "kkm_common.h"
@@ -162,6 +163,120 @@ __device__ __forceinline__ bool tile_of_block(int64_t ntiles, int64_t per_xcd, i
     return true;
 }
 
+// ---------------------------------------------------------------- FP32 product
+
+constexpr int GK = 32;        // k-slab staged in LDS per step (floats)
+constexpr int GLD = GK + 4;   // padded LDS row stride in floats (conflict-free b128 reads)
+
+struct F32Tile {
+    const float *X;
+    int64_t d, ldx;
+    int vec_x;  // rows 16-byte aligned
+    Epi e;
+};
+
+typedef float F32Lds[2][2][GM * GLD];
+
+__device__ __forceinline__ f32x4 load_row4(const F32Tile &a, int64_t row, int64_t col) {
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (row < a.e.n) {
+        const float *src = a.X + row * a.ldx + col;
+        if (a.vec_x && col + 3 < a.d) {
+            v = *reinterpret_cast<const f32x4 *>(src);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (col + u < a.d) v[u] = src[u];
+        }
+    }
+    return v;
+}
+
+// One 128 x 128 tile (bi, bj) of the FP32 product and its epilogue.
+template <typename OUT>
+__device__ __forceinline__ void f32_tile(const F32Tile &a, int64_t bi, int64_t bj, F32Lds &lds) {
+    const int64_t m0 = bi * GM, n0 = bj * GM;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int ld_row = tid >> 3;        // 8 threads per 32-float row slice
+    const int ld_col = (tid & 7) * 4;
+
+    f32x4 ra[4], rb[4];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ra[u] = load_row4(a, m0 + ld_row + 32 * u, k0 + ld_col);
+            rb[u] = load_row4(a, n0 + ld_row + 32 * u, k0 + ld_col);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            *reinterpret_cast<f32x4 *>(&lds[buf][0][(ld_row + 32 * u) * GLD + ld_col]) = ra[u];
+            *reinterpret_cast<f32x4 *>(&lds[buf][1][(ld_row + 32 * u) * GLD + ld_col]) = rb[u];
+        }
+    };
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int64_t nk = (a.d + GK - 1) / GK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+
+    // The 32x32x2 MFMA takes A[i][kk] from lane (kk*32 + i) and B[kk][j] from
+    // lane (kk*32 + j).  Within a slab the k index is permuted the same way for
+    // both operands (lane half h covers k = 16h .. 16h+15 across 16 MFMAs), so
+    // each lane fetches 16 consecutive floats with four b128 LDS reads.
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * GK);
+        const float *As = lds[buf][0];
+        const float *Bs = lds[buf][1];
+        f32x4 av[2][4], bv[2][4];
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+            const float *pa = As + (wr * 64 + mi * 32 + l32) * GLD + half * 16;
+            const float *pb = Bs + (wc * 64 + mi * 32 + l32) * GLD + half * 16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                av[mi][q] = *reinterpret_cast<const f32x4 *>(pa + 4 * q);
+                bv[mi][q] = *reinterpret_cast<const f32x4 *>(pb + 4 * q);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                        av[mi][s >> 2][s & 3], bv[ni][s >> 2][s & 3], acc[mi][ni], 0, 0, 0);
+        if (kt + 1 < nk) sstore(buf ^ 1);
+        __syncthreads();
+    }
+    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane);
+}
+
+// Squared norm of one FP32 row (Gaussian, FP32 product), by one whole wave.
+__device__ __forceinline__ void sqnorm_row(const float *x, int64_t d, float *nrm, int lane) {
+    float s = 0.f;
+    for (int64_t l = lane; l < d; l += kWave) s = fmaf(x[l], x[l], s);
+    s = wave_sum(s);
+    if (lane == 0) *nrm = s;
+}
+
 // ---------------------------------------------------------------- BF16 / FP8 product
 
 // A slab is 128 bytes of every row (64 bf16 or 128 fp8), staged in LDS with a
@@ -178,6 +293,12 @@ struct LowpTile {
 };
 
 typedef unsigned char LowpLds[2][2][GM * SLD];
+
+// Row length of the rounded matrix: d rounded up to whole slabs.
+inline int64_t padded_d(int64_t d, int32_t gram_prec) {
+    const int64_t per = (gram_prec == KKM_BF16) ? 64 : 128;
+    return (d + per - 1) / per * per;
+}
 
 // One 128 x 128 tile (bi, bj) of the product and its epilogue, by the 256
 // threads of a workgroup, staging through `lds`.

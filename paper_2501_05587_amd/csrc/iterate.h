@@ -34,12 +34,12 @@ struct Inst {
 };
 
 // A set of problems: `one` passed by value (table == nullptr), or a device
-// table of `count` problems whose blocks / clusters / sweep items are laid end
-// to end (prefix arrays of count + 1 entries).  active (nullable): a problem
-// with active[b] == 0 is skipped.
+// table of up to `count` live problems whose label blocks / clusters / sweep
+// items are laid end to end.  The prefix arrays have count + 1 entries; the
+// entries past the last live problem all hold the live total, so a table can
+// shrink between launches of a captured graph of fixed grid sizes.
 struct InstSet {
     const Inst *table;
-    const int32_t *active;
     const int64_t *blk_start, *cl_start, *item_start;
     int32_t count;
     Inst one;
@@ -51,6 +51,28 @@ struct InstGeom {
     int64_t L, nblk, nchunk, slots, ldp, nws_max;
 };
 
+// Reads of data that every lane of a workgroup takes from the same address and
+// that no kernel of the step writes, through the constant address space, so
+// they are scalar loads and the values stay in scalar registers.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) T *)(p);
+#else
+    return *p;  // the host pass only parses device functions
+#endif
+}
+
+__device__ __forceinline__ int32_t find_inst(const int64_t *start, int32_t count, int64_t g) {
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (uniform_load(start + mid) <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Geometry of a problem; L = 0 picks the default chunk length.
 InstGeom inst_geometry(int64_t n, int32_t k, int64_t L);
 size_t inst_workspace_bytes(const InstGeom &g);
@@ -61,12 +83,18 @@ int64_t inst_sweep_items(const InstGeom &g, int32_t k_store);
 // Sets the strip counts that depend on the element type of K.
 void inst_set_store(Inst *in, int32_t k_store);
 
-// The six kernels of one step over the whole set.  total_* are the grid sizes
-// (sums over the set); max_k sizes the dynamic LDS; vec: every K row is
-// 16-byte aligned.
+// The six kernels of one step over the whole set.  total_blocks and
+// total_clusters are grid sizes (sums over every problem the table can hold);
+// sweep_grid is the item count of a single problem, or for a table the size
+// of the persistent sweep grid; max_k sizes the dynamic LDS; vec: every K row
+// is 16-byte aligned.
 kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clusters,
-                       int64_t total_items, int32_t max_k, int32_t k_store, bool vec,
+                       int64_t sweep_grid, int32_t max_k, int32_t k_store, bool vec,
                        const int32_t *labels_in, int32_t *labels_out, hipStream_t stream);
+
+// Workgroups of the table-form sweep (K rows 16-byte aligned) that one compute
+// unit holds at once: the persistent sweep grid is this times the CU count.
+int sweep_blocks_per_cu(int32_t k_store);
 
 kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
                       int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,

@@ -19,10 +19,11 @@
 //      objective of the input labels, fused in one pass over the points.
 //
 // Every kernel takes an instance set: either one problem passed by value, or a
-// device table of problems whose blocks are laid end to end in one grid (a
-// block finds its problem by binary search in a prefix array).  Problems
-// marked inactive are skipped, so a captured sequence of launches can be
-// replayed while problems converge one by one.
+// device table of live problems whose blocks are laid end to end in one grid
+// (a block finds its problem by binary search in a prefix array; blocks past
+// the live total exit).  The table is rewritten on the device between steps,
+// so a captured sequence of launches can be replayed while problems converge
+// one by one.
 //
 // No floating-point atomics are used: every reduction runs in a fixed order,
 // so a step is bitwise repeatable.
@@ -35,47 +36,23 @@ namespace {
 constexpr int kPtsPerBlock = 256;          // points per block in the label kernels
 constexpr int kSweepThreads = 256;         // 4 waves
 
-// Reads of data that every lane of a workgroup takes from the same address and
-// that no kernel of the step writes, through the constant address space, so
-// they are scalar loads and the values stay in scalar registers.
-template <typename T>
-__device__ __forceinline__ T uniform_load(const T *p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return *(const __attribute__((address_space(4))) T *)(p);
-#else
-    return *p;  // the host pass only parses device functions
-#endif
-}
-
-__device__ __forceinline__ int32_t find_inst(const int64_t *start, int32_t count, int64_t g) {
-    int32_t lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (uniform_load(start + mid) <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Problem b and the block index within it for a flattened grid position g.
-// MULTI selects the table form at compile time: a run-time choice between the
-// two sources would leave the problem's fields in vector registers.
+// The problem and the block index within it for a flattened grid position g;
+// false when g lies past the live problems of a table.  MULTI selects the
+// table form at compile time: a run-time choice between the two sources would
+// leave the problem's fields in vector registers.
 template <bool MULTI>
-__device__ __forceinline__ Inst locate(const InstSet &s, const int64_t *start, int64_t g,
-                                       int32_t &b, int64_t &local) {
+__device__ __forceinline__ bool locate(const InstSet &s, const int64_t *start, int64_t g, Inst &in,
+                                       int64_t &local) {
     if constexpr (MULTI) {
-        b = find_inst(start, s.count, g);
+        if (g >= uniform_load(start + s.count)) return false;
+        const int32_t b = find_inst(start, s.count, g);
         local = g - uniform_load(start + b);
-        return uniform_load(s.table + b);
+        in = uniform_load(s.table + b);
     } else {
-        b = 0;
         local = g;
-        return s.one;
+        in = s.one;
     }
-}
-
-__device__ __forceinline__ bool inactive(const InstSet &s, int32_t b) {
-    return s.active && s.active[b] == 0;
+    return true;
 }
 
 // ---------------------------------------------------------------- 1. V in CSR form
@@ -84,10 +61,9 @@ __device__ __forceinline__ bool inactive(const InstSet &s, int32_t b) {
 template <bool MULTI>
 __global__ __launch_bounds__(kPtsPerBlock) void v_block_hist(InstSet s, const int32_t *labels_all) {
     extern __shared__ int32_t sh[];  // [k] + 1
-    int32_t b;
+    Inst in;
     int64_t lb;
-    const Inst in = locate<MULTI>(s, s.blk_start, blockIdx.x, b, lb);
-    if (inactive(s, b)) return;
+    if (!locate<MULTI>(s, s.blk_start, blockIdx.x, in, lb)) return;
     const int32_t k = in.k;
     const int32_t *labels = labels_all + in.lab_off;
     int32_t *hist = sh;
@@ -114,10 +90,9 @@ template <bool MULTI>
 __global__ __launch_bounds__(256) void v_cluster_scan(InstSet s) {
     __shared__ int32_t part[256];
     __shared__ int32_t carry;
-    int32_t b;
+    Inst in;
     int64_t c;
-    const Inst in = locate<MULTI>(s, s.cl_start, blockIdx.x, b, c);
-    if (inactive(s, b)) return;
+    if (!locate<MULTI>(s, s.cl_start, blockIdx.x, in, c)) return;
     const int64_t nblk = in.nblk;
     int32_t *row = in.blk_hist + c * nblk;
     if (threadIdx.x == 0) carry = 0;
@@ -158,10 +133,9 @@ __global__ __launch_bounds__(256) void v_cluster_scan(InstSet s) {
 template <bool MULTI>
 __global__ __launch_bounds__(kPtsPerBlock) void v_scatter(InstSet s, const int32_t *labels_all) {
     extern __shared__ int32_t sh[];  // off[k+1], wcnt[4][k]
-    int32_t b;
+    Inst in;
     int64_t lb;
-    const Inst in = locate<MULTI>(s, s.blk_start, blockIdx.x, b, lb);
-    if (inactive(s, b)) return;
+    if (!locate<MULTI>(s, s.blk_start, blockIdx.x, in, lb)) return;
     const int32_t k = in.k;
     const int32_t *labels = labels_all + in.lab_off;
     int32_t *off = sh;
@@ -263,14 +237,9 @@ template <> struct KRow<uint16_t> {
 // may span several clusters: the running sums are flushed to the partial-buffer
 // slot (chunk + cluster) whenever the cluster changes; the slot is unique per
 // (chunk, cluster) pair.
-template <typename T, bool VEC, bool MULTI>
-__global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(InstSet s,
-                                                                const int32_t *labels_all) {
+template <typename T, bool VEC>
+__device__ __forceinline__ void sweep_item(const Inst &in, int64_t item, const int32_t *labels_all) {
     constexpr int E = KRow<T>::E;
-    int32_t b;
-    int64_t item;
-    const Inst in = locate<MULTI>(s, s.item_start, blockIdx.x, b, item);
-    if (inactive(s, b)) return;
     if (*in.err != 0) return;
     const int64_t n = in.n;
     const int32_t k = in.k;
@@ -375,6 +344,32 @@ __global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(InstSet s,
     }
 }
 
+// One problem: one workgroup per item.  A table: a persistent grid whose
+// workgroups take contiguous, equal ranges of the live problems' items (all
+// items cost the same), looking a problem up only when the range crosses into
+// the next one.
+template <typename T, bool VEC, bool MULTI>
+__global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(InstSet s,
+                                                                const int32_t *labels_all) {
+    if constexpr (!MULTI) {
+        sweep_item<T, VEC>(s.one, blockIdx.x, labels_all);
+    } else {
+        const int64_t total = uniform_load(s.item_start + s.count);
+        const int64_t g0 = total * blockIdx.x / gridDim.x;
+        const int64_t g1 = total * (blockIdx.x + 1) / gridDim.x;
+        int32_t b = 0;
+        int64_t lo = 0, hi = 0;  // item range of problem b
+        for (int64_t g = g0; g < g1; ++g) {
+            if (g >= hi) {
+                b = find_inst(s.item_start, s.count, g);
+                lo = uniform_load(s.item_start + b);
+                hi = uniform_load(s.item_start + b + 1);
+            }
+            sweep_item<T, VEC>(uniform_load(s.table + b), g - lo, labels_all);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- 3. centroid norms
 
 // One workgroup per (problem, cluster): ||c_c||^2 = (1/|c|^2) sum_{i in c} S_ic,
@@ -382,10 +377,9 @@ __global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(InstSet s,
 template <int E, bool MULTI>
 __global__ __launch_bounds__(256) void centroid_norms(InstSet s) {
     __shared__ float ss[256], sc[256];
-    int32_t b;
+    Inst in;
     int64_t c;
-    const Inst in = locate<MULTI>(s, s.cl_start, blockIdx.x, b, c);
-    if (inactive(s, b)) return;
+    if (!locate<MULTI>(s, s.cl_start, blockIdx.x, in, c)) return;
     if (*in.err != 0) return;
     const int64_t nws = in.nws;
     const int64_t a = in.offsets[c], e = in.offsets[c + 1];
@@ -436,10 +430,9 @@ __global__ __launch_bounds__(kPtsPerBlock) void assign_fused(InstSet s,
     __shared__ double wJ[kPtsPerBlock / kWave];
     __shared__ long long wC[kPtsPerBlock / kWave];
     __shared__ bool last;
-    int32_t b;
+    Inst in;
     int64_t lb;
-    const Inst in = locate<MULTI>(s, s.blk_start, blockIdx.x, b, lb);
-    if (inactive(s, b)) return;
+    if (!locate<MULTI>(s, s.blk_start, blockIdx.x, in, lb)) return;
     const int32_t k = in.k;
     const int64_t L = in.L, ldp = in.ldp;
     const float *__restrict__ P = in.P;
@@ -618,7 +611,7 @@ namespace {
 
 template <bool MULTI>
 kkm_status step_launch_t(const InstSet &s, int64_t total_blocks, int64_t total_clusters,
-                         int64_t total_items, int32_t max_k, int32_t k_store, bool vec,
+                         int64_t sweep_grid, int32_t max_k, int32_t k_store, bool vec,
                          const int32_t *labels_in, int32_t *labels_out, hipStream_t stream) {
     const dim3 pb(kPtsPerBlock);
     const TimedSpan whole = timing_begin(TK_ITERATE, stream);
@@ -630,7 +623,7 @@ kkm_status step_launch_t(const InstSet &s, int64_t total_blocks, int64_t total_c
     hipLaunchKernelGGL(v_scatter<MULTI>, dim3((unsigned)total_blocks), pb,
                        (size_t)(max_k + 1 + 4 * max_k) * sizeof(int32_t), stream, s, labels_in);
     KKM_HIP(hipGetLastError());
-    const dim3 sg((unsigned)total_items), sb(kSweepThreads);
+    const dim3 sg((unsigned)sweep_grid), sb(kSweepThreads);
     const TimedSpan span = timing_begin(TK_SWEEP, stream);
     if (k_store == KKM_F32) {
         if (vec)
@@ -659,13 +652,23 @@ kkm_status step_launch_t(const InstSet &s, int64_t total_blocks, int64_t total_c
 
 }  // namespace
 
+int sweep_blocks_per_cu(int32_t k_store) {
+    int nb = 0;
+    hipError_t e = (k_store == KKM_F32)
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, spmm_row_sweep<float, true, true>, kSweepThreads, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, spmm_row_sweep<uint16_t, true, true>, kSweepThreads, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 4;
+}
+
 kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clusters,
-                       int64_t total_items, int32_t max_k, int32_t k_store, bool vec,
+                       int64_t sweep_grid, int32_t max_k, int32_t k_store, bool vec,
                        const int32_t *labels_in, int32_t *labels_out, hipStream_t stream) {
     if (s.table)
-        return step_launch_t<true>(s, total_blocks, total_clusters, total_items, max_k, k_store,
+        return step_launch_t<true>(s, total_blocks, total_clusters, sweep_grid, max_k, k_store,
                                    vec, labels_in, labels_out, stream);
-    return step_launch_t<false>(s, total_blocks, total_clusters, total_items, max_k, k_store, vec,
+    return step_launch_t<false>(s, total_blocks, total_clusters, sweep_grid, max_k, k_store, vec,
                                 labels_in, labels_out, stream);
 }
 

@@ -44,7 +44,18 @@ struct TimedSpan {
 TimedSpan timing_begin(int cls, hipStream_t stream);
 void timing_end(const TimedSpan &span, hipStream_t stream);
 
+// ---------------------------------------------------------------- argument checks
+
+kkm_status check_kernel(int32_t kernel_type, double gamma, double coef0, int32_t degree);
+kkm_status check_dtypes(int32_t gram_prec, int32_t k_store);
+size_t elem_bytes(int32_t k_store);
+
 // ---------------------------------------------------------------- shared launchers
+
+// flag = 1 if any of v[0..n) is not finite, else 0 (clears flag first).
+void flag_nonfinite(const float *v, int64_t n, int32_t *flag, hipStream_t stream);
+// p[0..n) = v by a kernel (graph-safe, unlike a memset node).
+void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream);
 
 size_t gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec);
 kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t kernel,

@@ -71,3 +71,67 @@ def test_workspace_sizes(lib):
     # partial sums stay a small fraction of the n x n matrix they summarise
     assert big < 0.002 * 200000 ** 2 * 4
     assert kkm.gram_workspace_bytes(1000, 16) >= 1000 * 4
+
+
+def test_instance_struct_layout_matches_header(tmp_path):
+    """The ctypes mirror of kkm_instance has the C struct's size and offsets."""
+    import subprocess
+
+    import paper_2501_05587_amd as kkm
+    src = tmp_path / "layout.c"
+    fields = [f[0] for f in kkm.KkmInstance._fields_]
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "kkm.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(kkm_instance));\n' +
+                   "".join('  printf("%%zu\\n", offsetof(kkm_instance, %s));\n' % f for f in fields) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [ctypes.sizeof(kkm.KkmInstance)] + [getattr(kkm.KkmInstance, f).offset for f in fields]
+    assert got == want
+
+
+def test_batched_validation_without_device_work(lib):
+    import paper_2501_05587_amd as kkm
+    I = kkm.KkmInstance
+    fake = 4096
+
+    def arr(*ps):
+        a = (I * len(ps))()
+        for i, p in enumerate(ps):
+            a[i] = p
+        return a
+
+    ok = I(fake, 100, 8, 8, 5, 2, 0.5, 0.0, 1, 0)
+    bad_k = I(fake, 10, 8, 8, 11, 2, 0.5, 0.0, 1, 0)
+    big_k = I(fake, 5000, 8, 8, 2000, 2, 0.5, 0.0, 1, 0)
+    bad_chunk = I(fake, 100, 8, 8, 5, 2, 0.5, 0.0, 1, -3)
+    bad_gamma = I(fake, 100, 8, 8, 5, 2, -1.0, 0.0, 1, 0)
+    obj = (ctypes.c_double * 2)()
+    its = (ctypes.c_int32 * 2)()
+    vp = ctypes.c_void_p
+
+    def fit(a, count, **kw):
+        return lib.kkm_fit_batched(a, count, kw.get("gp", 0), kw.get("ks", 0), kw.get("ep", 0),
+                                   vp(fake), kw.get("mi", 5), 1, 1, vp(fake), obj, its, None,
+                                   None, 0, None)
+
+    assert fit(arr(ok), 0) == -1
+    assert fit(arr(ok, bad_k), 2) == -1
+    assert b"problem 1" in lib.kkm_last_error()
+    assert fit(arr(big_k), 1) == -5
+    assert fit(arr(bad_chunk), 1) == -1
+    assert fit(arr(ok, bad_gamma), 2) == -1
+    assert b"problem 1" in lib.kkm_last_error() and b"gamma" in lib.kkm_last_error()
+    assert fit(arr(ok), 1, gp=5) == -1
+    assert fit(arr(ok), 1, ep=7) == -1
+    assert fit(arr(ok), 1, mi=-1) == -1
+    # workspace sizing is host arithmetic: every K is kept, rows padded to 64
+    ws = lib.kkm_fit_batched_workspace_bytes
+    one = ws(arr(ok), 1, 0, 0)
+    assert one >= 100 * 128 * 4
+    assert ws(arr(ok, ok), 2, 0, 0) >= 2 * 100 * 128 * 4
+    assert ws(arr(ok), 1, 1, 1) < one          # BF16 K is half the size
+    assert ws(arr(bad_k), 1, 0, 0) == 0
