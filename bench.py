@@ -176,6 +176,94 @@ def warm_labels(kkm, w, params, Xd, seed):
     return best[1], cheap
 
 
+def batched_leg(kkm, torch, dev, iters):
+    """The batched form: 512 uneven Gaussian-mixture problems, BF16 Gram, FP32 K."""
+    import numpy as np
+
+    import datagen
+    from paper_2501_05587_amd import autotune
+
+    specs = datagen.batched_instances(512)
+    t = time.perf_counter()
+    probs, labs = [], []
+    for s in specs:
+        X, _ = datagen.gmm(s["n"], s["d"], s["k"], s["sigma"], s["seed"])
+        probs.append(dict(X=torch.from_numpy(X).to(dev), k=s["k"], kernel=kkm.GAUSS,
+                          gamma=s["gamma"]))
+        labs.append(datagen.uniform_labels(s["n"], s["k"], s["label_seed"]))
+    l0 = torch.from_numpy(np.concatenate(labs)).to(dev)
+    nn = np.array([s["n"] for s in specs], dtype=np.float64)
+    dd = np.array([s["d"] for s in specs], dtype=np.float64)
+    k_bytes = float((nn * nn).sum() * 4)           # every K read once per step
+    gram_flops = float((nn * (nn + 1) * dd).sum())  # upper triangles, 2 flops per term
+    log("batched: %d problems, sum n %d, sum K %.1f GB, generated in %.1f s" % (
+        len(specs), int(nn.sum()), k_bytes / 1e9, time.perf_counter() - t))
+    table = autotune.load(torch=torch)
+    tuned = autotune.apply(probs, table, 0)
+    ws_bytes = max(kkm.kkm_fit_batched_workspace_bytes(ps, kkm.BF16, kkm.F32)
+                   for ps in (tuned, probs))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    lab = torch.empty_like(l0)
+
+    def run(ps, graph=True, max_iter=iters, conv=False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = kkm.kkm_fit_batched(ps, l0, gram_prec=kkm.BF16, k_store=kkm.F32, max_iter=max_iter,
+                                check_convergence=conv, use_graph=graph, labels_out=lab, ws=ws)
+        torch.cuda.synchronize()
+        r["wall_s"] = time.perf_counter() - t0
+        return r
+
+    run(tuned)  # warm-up
+    kkm.kkm_timing_enable(True)
+    r_tuned = run(tuned)
+    tim = kkm.kkm_timing_read()
+    kkm.kkm_timing_enable(False)
+    r_default = run(probs)
+    kkm.kkm_timing_enable(True)
+    r_eager = run(tuned, graph=False)
+    tim_e = kkm.kkm_timing_read()
+    kkm.kkm_timing_enable(False)
+    r_conv = run(tuned, max_iter=300, conv=True)
+    per_step = r_tuned["times_ms"][1] / iters
+    gram_ms = tim["gram"][0] / max(tim["gram"][1], 1)
+    sweep_ms = tim_e["sweep"][0] / max(tim_e["sweep"][1], 1)
+    out = {
+        "workload": "512 problems: n U{256..16384}, d in {32,64,128,256}, k U{2..64}, "
+                    "k-component mixtures sigma 0.3, gaussian gamma=1/d",
+        "problems": len(specs), "sum_n": int(nn.sum()), "sum_K_bytes": k_bytes,
+        "gram": "bf16 mfma, persistent tile queue", "k_store": "f32",
+        "iterations": iters, "graph": True,
+        "tuned_table": bool(table), "tuned_chunk_rows": sorted(set(p["chunk_rows"] for p in tuned)),
+        "gram_ms": gram_ms,
+        "gram_achieved_tflops": gram_flops / (gram_ms * 1e-3) / 1e12,
+        "gram_frac_bf16_mfma": gram_flops / (gram_ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFS,
+        "gram_write_gbs": k_bytes / (gram_ms * 1e-3) / 1e9,
+        "gram_write_frac_hbm": k_bytes / (gram_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "step_ms": per_step,
+        "aggregate_gbs": k_bytes / (per_step * 1e-3) / 1e9,
+        "frac_hbm": k_bytes / (per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "step_ms_default_chunk_rows": r_default["times_ms"][1] / iters,
+        "step_ms_eager": r_eager["times_ms"][1] / iters,
+        "sweep_ms": sweep_ms,
+        "sweep_frac_hbm": k_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "iters_per_s": iters / (r_tuned["times_ms"][1] * 1e-3),
+        "to_convergence": {"seconds": r_conv["wall_s"], "gram_ms": r_conv["times_ms"][0],
+                           "loop_ms": r_conv["times_ms"][1],
+                           "iters_max": int(r_conv["iters"].max()),
+                           "iters_median": float(np.median(r_conv["iters"])),
+                           "iters_min": int(r_conv["iters"].min())},
+    }
+    del ws
+    torch.cuda.empty_cache()
+    log("batched: gram %.1f ms, %.2f ms/step (%.0f GB/s, %.3f of HBM), default chunks %.2f ms, "
+        "eager %.2f ms; converged in %.3f s (max %d steps)" % (
+            gram_ms, per_step, out["aggregate_gbs"], out["frac_hbm"],
+            out["step_ms_default_chunk_rows"], out["step_ms_eager"], r_conv["wall_s"],
+            out["to_convergence"]["iters_max"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +276,9 @@ def main():
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched form and print its record")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -203,6 +294,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batched_only:
+        print(json.dumps(batched_leg(kkm, torch, torch.device("cuda:0"), args.iters or 30)),
+              flush=True)
         return
 
     w = datagen.WORKLOADS["gmm200k"]
@@ -344,6 +439,7 @@ def main():
     else:
         del K
     torch.cuda.empty_cache()
+    batched = None if args.no_batched else batched_leg(kkm, torch, dev, iters)
 
     out = {
         "metric": METRIC,
@@ -366,6 +462,7 @@ def main():
         "iter_ms": iter_ms,
         "plain_fp32_to_convergence": plain,
         "mixed_learned_to_convergence": learned,
+        "batched": batched,
         "roofline": roof,
         "roofline_gram": roof_g,
         "cpu_baseline": None,
