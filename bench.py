@@ -45,11 +45,11 @@ BF16_MFMA_PEAK_TFS = 2500.0
 # WRITE_SIZE all of them).  Valid only while the kernel's sources hash to the
 # recorded value; otherwise the traffic is reported as null.
 TRAFFIC = {
-    "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/kkm_common.h"],
+    "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
                        "sha256": "ad7eb214be00111fbc40297312c351c754586a69032f9ad3dc9f5054c7063be3",
                        "n": 200000, "fetch_kib": 78170184.08, "write_kib": 84946.79,
                        "fetch_scale": 1.9999, "write_scale": 1.0},
-    "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/kkm_common.h"],
+    "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_tile.h", "csrc/kkm_common.h"],
                       "sha256": "1d2d0a36aa3a5eb89125e6a1b3eb7da4d9cc78510b961bdfa065156d686e8c8c",
                       "n": 200000, "fetch_kib": 317951206.94, "write_kib": 188456126.5,
                       "fetch_scale": 1.9999, "write_scale": 1.0},

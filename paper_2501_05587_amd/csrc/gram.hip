@@ -31,27 +31,21 @@ using namespace gt;
 
 // ---------------------------------------------------------------- FP32 product
 
-struct F32Args {
-    F32Tile t;
-    int64_t ntiles, per_xcd;
-};
-
 template <typename OUT>
-__global__ __launch_bounds__(GTHREADS, 2) void gram_f32_mfma(F32Args a) {
+__global__ __launch_bounds__(GTHREADS, 2) void gram_f32_mfma(F32Tile a, TileOrder o) {
     __shared__ __attribute__((aligned(16))) F32Lds lds;
     int64_t bi, bj;
-    if (!tile_of_block(a.ntiles, a.per_xcd, bi, bj)) return;
-    f32_tile<OUT>(a.t, bi, bj, lds);
+    if (!tile_of_block(o, bi, bj)) return;
+    f32_tile<OUT>(a, bi, bj, lds);
 }
 
 // ---------------------------------------------------------------- BF16 / FP8 product
 
 template <int PREC, typename OUT>
-__global__ __launch_bounds__(GTHREADS, 2) void gram_lowp_mfma(LowpTile a, int64_t ntiles,
-                                                              int64_t per_xcd) {
+__global__ __launch_bounds__(GTHREADS, 2) void gram_lowp_mfma(LowpTile a, TileOrder o) {
     __shared__ __attribute__((aligned(16))) LowpLds lds;
     int64_t bi, bj;
-    if (!tile_of_block(ntiles, per_xcd, bi, bj)) return;
+    if (!tile_of_block(o, bi, bj)) return;
     lowp_tile<PREC, OUT>(a, bi, bj, lds);
 }
 
@@ -77,6 +71,14 @@ __global__ __launch_bounds__(256) void quantize_rows(const float *X, int64_t n, 
     const int64_t eb = (PREC == KKM_BF16) ? 2 : 1;
     quantize_row<PREC>(X + row * ldx, d, dpad, Xq + row * dpad * eb, nrm + row, scale + row,
                        threadIdx.x & 63);
+}
+
+// log2 of the tile group edge of the launch order: 8 x 8 groups, so the 64
+// tiles an XCD holds at once (32 CUs x 2 workgroups) read 16 operand panels.
+int group_log2(int64_t d, int32_t gram_prec) {
+    (void)d;
+    (void)gram_prec;
+    return 3;
 }
 
 }  // namespace
@@ -117,10 +119,8 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
     const uintptr_t kaddr = reinterpret_cast<uintptr_t>(K);
     e.vec_k = (k_store == KKM_F32) ? (((ldk % 4) == 0) && ((kaddr & 15) == 0))
                                    : (((ldk % 4) == 0) && ((kaddr & 7) == 0));
-    const int64_t nb = (n + GM - 1) / GM;
-    const int64_t ntiles = nb * (nb + 1) / 2;
-    const int64_t per_xcd = (ntiles + 7) / 8;
-    const int64_t grid = per_xcd * 8;
+    const TileOrder order = tile_order(n, group_log2(d, gram_prec));
+    const int64_t grid = order.per_xcd * 8;
     if (grid > 0x7fffffff) {
         set_error("kkm_gram: n=%lld needs more than 2^31 tiles", (long long)n);
         return KKM_ERR_UNSUPPORTED;
@@ -132,21 +132,19 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
             hipLaunchKernelGGL(row_sqnorms, dim3(qgrid), dim3(256), 0, stream, X, n, d, ldx, nrm);
             KKM_HIP(hipGetLastError());
         }
-        F32Args a;
-        a.t.X = X;
-        a.t.d = d;
-        a.t.ldx = ldx;
-        a.t.vec_x = ((ldx % 4) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
-        a.t.e = e;
-        a.ntiles = ntiles;
-        a.per_xcd = per_xcd;
+        F32Tile a;
+        a.X = X;
+        a.d = d;
+        a.ldx = ldx;
+        a.vec_x = ((ldx % 4) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+        a.e = e;
         const TimedSpan span = timing_begin(TK_GRAM, stream);
         if (k_store == KKM_F32)
             hipLaunchKernelGGL(gram_f32_mfma<float>, dim3((unsigned)grid), dim3(GTHREADS), 0,
-                               stream, a);
+                               stream, a, order);
         else
             hipLaunchKernelGGL(gram_f32_mfma<uint16_t>, dim3((unsigned)grid), dim3(GTHREADS), 0,
-                               stream, a);
+                               stream, a, order);
         KKM_HIP(hipGetLastError());
         timing_end(span, stream);
         return KKM_OK;
@@ -172,13 +170,13 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
     const TimedSpan span = timing_begin(TK_GRAM, stream);
     const dim3 g((unsigned)grid), b(GTHREADS);
     if (gram_prec == KKM_BF16 && k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, float>), g, b, 0, stream, a, ntiles, per_xcd);
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, float>), g, b, 0, stream, a, order);
     else if (gram_prec == KKM_BF16)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, uint16_t>), g, b, 0, stream, a, ntiles, per_xcd);
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, uint16_t>), g, b, 0, stream, a, order);
     else if (k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, float>), g, b, 0, stream, a, ntiles, per_xcd);
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, float>), g, b, 0, stream, a, order);
     else
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, uint16_t>), g, b, 0, stream, a, ntiles, per_xcd);
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, uint16_t>), g, b, 0, stream, a, order);
     KKM_HIP(hipGetLastError());
     timing_end(span, stream);
     return KKM_OK;

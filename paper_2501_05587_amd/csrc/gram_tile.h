@@ -76,24 +76,40 @@ template <> struct Store<uint16_t> {
     }
 };
 
-// Writes one wave's 64 x 64 sub-tile (2 x 2 blocks of 32 x 32 accumulators).
-// Accumulator register r of lane l holds output row 8*(r/4) + 4*(l/32) + r%4
-// and column l%32 of its 32 x 32 block.
+// Row stride (floats) of the transposed tile staged in LDS by the epilogue: the
+// pad spreads the 16-byte stores of lanes holding consecutive columns over all
+// banks.
+constexpr int TS = GM + 4;
+constexpr size_t EPI_LDS_BYTES = sizeof(float) * GM * TS;
+
+// Writes the 128 x 128 tile held by the four waves (each a 64 x 64 sub-tile as
+// 2 x 2 blocks of 32 x 32 accumulators).  Accumulator register r of lane l
+// holds output row 8*(r/4) + 4*(l/32) + r%4 and column l%32 of its block.
+//
+// Off the diagonal every value goes to K[i][j] straight from the registers (32
+// lanes write 32 consecutive floats of a row) and to K[j][i] through `T`, the
+// tile transposed in LDS, so that the mirrored rows also leave as whole
+// contiguous rows rather than scattered 16-byte pieces.  `T` (EPI_LDS_BYTES)
+// may alias the operand buffers: the caller's last barrier has retired every
+// read of them, and the trailing barrier here retires every read of `T`.
 template <typename OUT>
 __device__ __forceinline__ void epilogue(const Epi &e, const f32x16 (&acc)[2][2], int64_t m0,
-                                         int64_t n0, bool diag_tile, int wr, int wc, int lane) {
+                                         int64_t n0, bool diag_tile, int wr, int wc, int lane,
+                                         float *T) {
     const int half = lane >> 5, l32 = lane & 31;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi) {
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni) {
-            const int64_t gj = n0 + wc * 64 + ni * 32 + l32;
+            const int jj = wc * 64 + ni * 32 + l32;
+            const int64_t gj = n0 + jj;
             const bool jin = gj < e.n;
             const float nrm_j = (e.kernel == KKM_GAUSS && jin) ? e.nrm[gj] : 0.f;
             const float s_j = (e.scale && jin) ? e.scale[gj] : 1.f;
 #pragma unroll
             for (int rg = 0; rg < 4; ++rg) {
-                const int64_t gi0 = m0 + wr * 64 + mi * 32 + 8 * rg + 4 * half;
+                const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+                const int64_t gi0 = m0 + ii0;
                 float v[4], b[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -105,21 +121,16 @@ __device__ __forceinline__ void epilogue(const Epi &e, const f32x16 (&acc)[2][2]
                     v[r] = kappa_from_dot(b[r], nrm_i, nrm_j, e.kernel, e.gamma, e.coef0,
                                           e.degree);
                 }
-                if (!jin) continue;
                 if (!diag_tile) {
                     // K[gi][gj]: the 32 lanes of a half write 32 consecutive entries of a row
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (gi0 + r < e.n) Store<OUT>::one(e.K, (gi0 + r) * e.ldk + gj, v[r]);
-                    // mirror K[gj][gi0 .. gi0+3]: four consecutive entries of row gj
-                    if (e.vec_k && gi0 + 3 < e.n) {
-                        Store<OUT>::four(e.K, gj * e.ldk + gi0, v);
-                    } else {
+                    if (jin) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            if (gi0 + r < e.n) Store<OUT>::one(e.K, gj * e.ldk + gi0 + r, v[r]);
+                            if (gi0 + r < e.n) Store<OUT>::one(e.K, (gi0 + r) * e.ldk + gj, v[r]);
                     }
-                } else {
+                    const f32x4 w = {v[0], v[1], v[2], v[3]};
+                    *reinterpret_cast<f32x4 *>(T + jj * TS + ii0) = w;
+                } else if (jin) {
                     // diagonal tile: the upper triangle is the source of truth
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -141,6 +152,26 @@ __device__ __forceinline__ void epilogue(const Epi &e, const f32x16 (&acc)[2][2]
             }
         }
     }
+    if (diag_tile) return;  // uniform across the workgroup
+    __syncthreads();
+    // K[n0 + jj][m0 .. m0 + 127]: 32 threads per row, 4 entries each, 8 rows per
+    // pass.  Off the diagonal m0 + 127 < n0 < n, so only the row needs a check.
+    const int tid = threadIdx.x;
+    const int c4 = (tid & 31) * 4;
+    for (int jj = tid >> 5; jj < GM; jj += GTHREADS / 32) {
+        const int64_t gj = n0 + jj;
+        if (gj >= e.n) break;
+        const f32x4 w = *reinterpret_cast<const f32x4 *>(T + jj * TS + c4);
+        const float v[4] = {w[0], w[1], w[2], w[3]};
+        const int64_t idx = gj * e.ldk + m0 + c4;
+        if (e.vec_k) {
+            Store<OUT>::four(e.K, idx, v);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Store<OUT>::one(e.K, idx + r, v[r]);
+        }
+    }
+    __syncthreads();
 }
 
 // Upper-triangle tile t -> (bi, bj), bi <= bj, column by column.
@@ -152,15 +183,40 @@ __device__ __forceinline__ void tile_coords(int64_t t, int64_t &bi, int64_t &bj)
     bi = t - j * (j + 1) / 2;
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous
-// range of tiles so that tiles sharing an operand panel share an L2.
-__device__ __forceinline__ bool tile_of_block(int64_t ntiles, int64_t per_xcd, int64_t &bi,
-                                              int64_t &bj) {
+// Launch order of the tiles.  Positions walk g x g groups of tiles (g a power
+// of two): the upper triangle of groups column by column, each group column
+// by column.  A position whose tile lies below the diagonal or past the edge
+// has no tile.  Workgroups are dealt to the 8 XCDs round-robin; each XCD gets
+// a contiguous range of positions, so the tiles one XCD runs together share
+// 2g operand panels in its L2 instead of one panel per tile.
+struct TileOrder {
+    int64_t nb;        // tiles per side
+    int64_t npos;      // positions: G (G + 1) / 2 * g^2, G = ceil(nb / g)
+    int64_t per_xcd;   // positions per XCD
+    int lg;            // log2 g
+};
+
+inline TileOrder tile_order(int64_t n, int lg) {
+    TileOrder o;
+    o.nb = (n + GM - 1) / GM;
+    o.lg = lg;
+    const int64_t G = (o.nb + (int64_t(1) << lg) - 1) >> lg;
+    o.npos = (G * (G + 1) / 2) << (2 * lg);
+    o.per_xcd = (o.npos + 7) / 8;
+    return o;
+}
+
+__device__ __forceinline__ bool tile_of_block(const TileOrder &o, int64_t &bi, int64_t &bj) {
     const int64_t pid = blockIdx.x;
-    const int64_t t = (pid % 8) * per_xcd + pid / 8;
-    if (t >= ntiles) return false;
-    tile_coords(t, bi, bj);
-    return true;
+    const int64_t t = (pid % 8) * o.per_xcd + pid / 8;
+    if (t >= o.npos) return false;
+    int64_t I, J;
+    tile_coords(t >> (2 * o.lg), I, J);
+    const int64_t w = t & ((int64_t(1) << (2 * o.lg)) - 1);
+    const int64_t g1 = (int64_t(1) << o.lg) - 1;
+    bi = (I << o.lg) + (w & g1);
+    bj = (J << o.lg) + (w >> o.lg);
+    return bi <= bj && bj < o.nb;
 }
 
 // ---------------------------------------------------------------- FP32 product
@@ -266,7 +322,8 @@ __device__ __forceinline__ void f32_tile(const F32Tile &a, int64_t bi, int64_t b
         if (kt + 1 < nk) sstore(buf ^ 1);
         __syncthreads();
     }
-    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane);
+    static_assert(sizeof(F32Lds) >= EPI_LDS_BYTES, "epilogue tile does not fit");
+    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane, &lds[0][0][0]);
 }
 
 // Squared norm of one FP32 row (Gaussian, FP32 product), by one whole wave.
@@ -399,7 +456,9 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
         if (kt + 1 < a.nslab) sstore(buf ^ 1);
         __syncthreads();
     }
-    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane);
+    static_assert(sizeof(LowpLds) >= EPI_LDS_BYTES, "epilogue tile does not fit");
+    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane,
+                  reinterpret_cast<float *>(&lds[0][0][0]));
 }
 
 __device__ __forceinline__ float wave_max(float v) {

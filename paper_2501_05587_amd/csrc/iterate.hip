@@ -197,10 +197,12 @@ __global__ __launch_bounds__(kPtsPerBlock) void v_scatter(InstSet s, const int32
 template <typename T> struct KRow;
 template <> struct KRow<float> {
     static constexpr int E = 4;
-    template <bool VEC>
-    static __device__ __forceinline__ void load(const float *row, int64_t col, int64_t n,
-                                                float (&v)[E]) {
-        if (VEC && col + E - 1 < n) {
+    // 16-byte rows go through 64-bit global addresses: measured faster for FP32
+    // K than buffer loads (25.7 vs 26.3 ms per 160 GB sweep)
+    static constexpr bool kBuffer = false;
+    static __device__ __forceinline__ void load_vec(const float *row, int64_t col, int64_t n,
+                                                    float (&v)[E]) {
+        if (col + E - 1 < n) {
             const f32x4 w = *reinterpret_cast<const f32x4 *>(row + col);
 #pragma unroll
             for (int u = 0; u < E; ++u) v[u] = w[u];
@@ -209,27 +211,63 @@ template <> struct KRow<float> {
             for (int u = 0; u < E; ++u) v[u] = (col + u < n) ? row[col + u] : 0.f;
         }
     }
+    // element loads of a row of any alignment (0 past column n)
+    static __device__ __forceinline__ void load(const float *row, int64_t col, int64_t n,
+                                                float (&v)[E]) {
+#pragma unroll
+        for (int u = 0; u < E; ++u) v[u] = (col + u < n) ? row[col + u] : 0.f;
+    }
+    // 16-byte load at byte offset voff of the row described by r (0 past its end)
+    static __device__ __forceinline__ void load_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                    float (&v)[E]) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+#pragma unroll
+        for (int u = 0; u < E; ++u) v[u] = __uint_as_float(w[u]);
+    }
 };
 template <> struct KRow<uint16_t> {
     static constexpr int E = 8;
-    template <bool VEC>
+    // buffer loads: one shared 32-bit lane offset instead of a 64-bit address
+    // per row lets the unpacked rows fit 80 VGPRs (6 waves per SIMD instead of
+    // 4); measured 13.2 vs 15.1 ms per 80 GB sweep
+    static constexpr bool kBuffer = true;
     static __device__ __forceinline__ void load(const uint16_t *row, int64_t col, int64_t n,
                                                 float (&v)[E]) {
-        if (VEC && col + E - 1 < n) {
-            const uint4 w = *reinterpret_cast<const uint4 *>(row + col);
-            const uint32_t p[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                v[2 * u] = __uint_as_float(p[u] << 16);
-                v[2 * u + 1] = __uint_as_float(p[u] & 0xffff0000u);
-            }
-        } else {
+        for (int u = 0; u < E; ++u)
+            v[u] = (col + u < n) ? __uint_as_float((uint32_t)row[col + u] << 16) : 0.f;
+    }
+    static __device__ __forceinline__ void load_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                    float (&v)[E]) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
 #pragma unroll
-            for (int u = 0; u < E; ++u)
-                v[u] = (col + u < n) ? __uint_as_float((uint32_t)row[col + u] << 16) : 0.f;
+        for (int u = 0; u < 4; ++u) {
+            v[2 * u] = __uint_as_float(w[u] << 16);
+            v[2 * u + 1] = __uint_as_float(w[u] & 0xffff0000u);
         }
     }
 };
+
+// Buffer resource of one K row (gfx9 raw buffer: stride 0, range in bytes,
+// 32-bit data format word).  Loads through it take one 32-bit lane offset
+// shared by every row, and return 0 beyond the range.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *row, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(row), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+// The E entries of one K row at this lane's columns.  VEC: rows 16-byte
+// aligned (ldk a multiple of E); otherwise element loads.
+template <typename T, bool VEC>
+__device__ __forceinline__ void load_row(const T *row, int64_t col, int64_t n, uint32_t voff,
+                                         uint32_t rbytes, float (&v)[KRow<T>::E]) {
+    if constexpr (VEC && KRow<T>::kBuffer)
+        KRow<T>::load_buf(row_rsrc(row, rbytes), voff, v);
+    else if constexpr (VEC)
+        KRow<T>::load_vec(row, col, n, v);
+    else
+        KRow<T>::load(row, col, n, v);
+}
 
 // One work item = (column strip, chunk of L positions in V's CSR order).  Each
 // lane owns E consecutive columns (one 16-byte load per row); a wave covers
@@ -259,6 +297,11 @@ __device__ __forceinline__ void sweep_item(const Inst &in, int64_t item, const i
     const int64_t col = wave_strip * (kWave * E) + (int64_t)lane * E;
     const int64_t p_begin = q * L;
     const int64_t p_end = min(n, p_begin + L);
+    // VEC: every row is read with 16-byte buffer loads at this lane's byte
+    // offset; columns in [n, ldk) are read but never used (their sums are not
+    // stored and their labels are -1), and the range ends the row at ldk.
+    const uint32_t voff = (uint32_t)(col * (int64_t)sizeof(T));
+    const uint32_t rbytes = (uint32_t)(ldk * (int64_t)sizeof(T));
 
     // labels of this lane's columns (for z: the own-cluster entries)
     int32_t own[E];
@@ -282,18 +325,27 @@ __device__ __forceinline__ void sweep_item(const Inst &in, int64_t item, const i
 #pragma unroll
         for (int u = 0; u < E; ++u) sum[u] = e[u] = 0.f;
         for (; p + 8 <= seg_end; p += 8) {
-            float v[8][E];
+            // pairwise sum of 8 rows, ((r0+r1)+(r2+r3)) + ((r4+r5)+(r6+r7)), taken
+            // as two halves so that only four rows are unpacked at a time
+            float blk[E];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int64_t j = __builtin_amdgcn_readfirstlane(perm[p + r]);
-                KRow<T>::template load<VEC>(K + j * ldk, col, n, v[r]);
+            for (int h = 0; h < 2; ++h) {
+                float v[4][E];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t j = __builtin_amdgcn_readfirstlane(perm[p + 4 * h + r]);
+                    load_row<T, VEC>(K + j * ldk, col, n, voff, rbytes, v[r]);
+                }
+#pragma unroll
+                for (int u = 0; u < E; ++u) {
+                    const float q = (v[0][u] + v[1][u]) + (v[2][u] + v[3][u]);
+                    blk[u] = h ? blk[u] + q : q;
+                }
             }
 #pragma unroll
             for (int u = 0; u < E; ++u) {
-                const float blk = ((v[0][u] + v[1][u]) + (v[2][u] + v[3][u])) +
-                                  ((v[4][u] + v[5][u]) + (v[6][u] + v[7][u]));
                 float t, er;
-                two_sum(sum[u], blk, t, er);
+                two_sum(sum[u], blk[u], t, er);
                 sum[u] = t;
                 e[u] += er;
             }
@@ -305,7 +357,7 @@ __device__ __forceinline__ void sweep_item(const Inst &in, int64_t item, const i
             for (; p < seg_end; ++p) {
                 const int64_t j = __builtin_amdgcn_readfirstlane(perm[p]);
                 float v[E];
-                KRow<T>::template load<VEC>(K + j * ldk, col, n, v);
+                load_row<T, VEC>(K + j * ldk, col, n, voff, rbytes, v);
 #pragma unroll
                 for (int u = 0; u < E; ++u) blk[u] += v[u];
             }
