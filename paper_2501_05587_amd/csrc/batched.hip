@@ -14,8 +14,7 @@
 //                 max_iter) and rewrites the table in place.  The grid sizes
 //                 are those of the whole batch, so the same launches can be
 //                 captured once (one graph per label-buffer parity) and
-//                 replayed; the sweep is a persistent grid over the live
-//                 problems' items.
+//                 replayed.
 //   4. final pass one more step over the problems that stopped at max_iter,
 //                 for the objective of their final labels.
 //
@@ -243,7 +242,7 @@ __global__ __launch_bounds__(kCtlThreads) void batch_control(Ctl c, int32_t mode
 
 struct Plan {
     int32_t count = 0;
-    int64_t total_n = 0, total_blocks = 0, total_clusters = 0, total_tiles = 0;
+    int64_t total_n = 0, total_blocks = 0, total_clusters = 0, total_items = 0, total_tiles = 0;
     int32_t max_k = 0;
     size_t bytes = 0;
     // device pointers (valid when carved from a real base)
@@ -356,10 +355,11 @@ void make_plan(const kkm_instance *inst, int32_t count, int32_t gram_prec, int32
     p.queue = c.take<unsigned long long>(1);
     p.bytes = c.bytes();
 
-    p.total_blocks = p.total_clusters = 0;
+    p.total_blocks = p.total_clusters = p.total_items = 0;
     p.max_k = 0;
     for (int32_t b = 0; b < count; ++b) {
         p.total_blocks += geo[b].first.nblk;
+        p.total_items += inst_sweep_items(geo[b].first, k_store);
         p.total_clusters += inst[b].k;
         p.max_k = std::max(p.max_k, inst[b].k);
     }
@@ -539,7 +539,7 @@ extern "C" kkm_status kkm_fit_batched(const kkm_instance *inst, int32_t count, i
     Plan p;
     make_plan(inst, count, gram_prec, k_store, empty_policy, nullptr, p);
     if ((p.total_n + 255) / 4 > 0x7fffffffLL || p.total_blocks > 0x7fffffffLL ||
-        p.total_clusters > 0x7fffffffLL) {
+        p.total_clusters > 0x7fffffffLL || p.total_items > 0x7fffffffLL) {
         set_error("kkm_fit_batched: the batch is too large for one grid");
         return KKM_ERR_UNSUPPORTED;
     }
@@ -565,7 +565,7 @@ extern "C" kkm_status kkm_fit_batched(const kkm_instance *inst, int32_t count, i
     int dev = 0, cus = 0;
     KKM_HIP(hipGetDevice(&dev));
     KKM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t sweep_grid = std::max<int64_t>(1, (int64_t)cus * sweep_blocks_per_cu(k_store));
+    const int64_t sweep_grid = p.total_items;
 
     // tables (pageable host memory: wait for the copies before it goes away)
     KKM_HIP(hipMemcpyAsync(p.full, p.h_full.data(), sizeof(Inst) * count, hipMemcpyHostToDevice, s));

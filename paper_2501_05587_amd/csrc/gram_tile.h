@@ -76,99 +76,144 @@ template <> struct Store<uint16_t> {
     }
 };
 
-// Row stride (floats) of the transposed tile staged in LDS by the epilogue: the
-// pad spreads the 16-byte stores of lanes holding consecutive columns over all
-// banks.
+// Row stride (floats) of the tile staged in LDS by the epilogue: the pad
+// spreads the 16-byte accesses of lanes holding consecutive rows over all banks.
 constexpr int TS = GM + 4;
 constexpr size_t EPI_LDS_BYTES = sizeof(float) * GM * TS;
+
+// The squared norms (and FP8 row scales) of a tile's 128 rows and 128
+// columns, staged in LDS when the tile starts so that their loads overlap the
+// product: [0, 128) rows m0.., [128, 256) rows n0...  Needs a barrier before
+// the epilogue reads them (the main loop has several).
+__device__ __forceinline__ void stage_norms(const Epi &e, int64_t m0, int64_t n0, float *rn,
+                                            float *rs) {
+    const int t = threadIdx.x;
+    const int64_t g = (t < GM) ? m0 + t : n0 + (t - GM);
+    const bool in = g < e.n;
+    rn[t] = (e.kernel == KKM_GAUSS && in) ? e.nrm[g] : 0.f;
+    rs[t] = (e.scale && in) ? e.scale[g] : 1.f;
+}
 
 // Writes the 128 x 128 tile held by the four waves (each a 64 x 64 sub-tile as
 // 2 x 2 blocks of 32 x 32 accumulators).  Accumulator register r of lane l
 // holds output row 8*(r/4) + 4*(l/32) + r%4 and column l%32 of its block.
 //
-// Off the diagonal every value goes to K[i][j] straight from the registers (32
-// lanes write 32 consecutive floats of a row) and to K[j][i] through `T`, the
-// tile transposed in LDS, so that the mirrored rows also leave as whole
-// contiguous rows rather than scattered 16-byte pieces.  `T` (EPI_LDS_BYTES)
-// may alias the operand buffers: the caller's last barrier has retired every
-// read of them, and the trailing barrier here retires every read of `T`.
+// Off the diagonal kappa replaces the accumulators in place, then the tile
+// goes through `T` twice, transposed for K[j][i] and as is for K[i][j], so
+// that both leave as whole rows of 4-element vector stores.  `T`
+// (EPI_LDS_BYTES) may alias the operand buffers: the caller's last barrier
+// has retired every read of them.  The trailing barrier retires every read of
+// `T`, `rn` and `rs` before the workgroup's next tile.
 template <typename OUT>
-__device__ __forceinline__ void epilogue(const Epi &e, const f32x16 (&acc)[2][2], int64_t m0,
+__device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int64_t m0,
                                          int64_t n0, bool diag_tile, int wr, int wc, int lane,
-                                         float *T) {
+                                         float *T, const float *rn, const float *rs) {
     const int half = lane >> 5, l32 = lane & 31;
+    const int tid = threadIdx.x;
+    const int c4 = (tid & 31) * 4;
+    if (!diag_tile) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) {
+                const int jj = wc * 64 + ni * 32 + l32;
+                const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
+#pragma unroll
+                for (int rg = 0; rg < 4; ++rg) {
+                    const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float b = acc[mi][ni][4 * rg + r];
+                        if (e.scale) b *= rs[ii0 + r] * s_j;
+                        acc[mi][ni][4 * rg + r] = kappa_from_dot(b, rn[ii0 + r], nrm_j, e.kernel,
+                                                                 e.gamma, e.coef0, e.degree);
+                    }
+                    // transposed: T[jj][ii0 .. ii0+3]
+                    const f32x4 w = {acc[mi][ni][4 * rg], acc[mi][ni][4 * rg + 1],
+                                     acc[mi][ni][4 * rg + 2], acc[mi][ni][4 * rg + 3]};
+                    *reinterpret_cast<f32x4 *>(T + jj * TS + ii0) = w;
+                }
+            }
+        __syncthreads();
+        // K[n0 + jj][m0 .. m0 + 127]; off the diagonal m0 + 127 < n0 < n
+        for (int jj = tid >> 5; jj < GM; jj += GTHREADS / 32) {
+            const int64_t gj = n0 + jj;
+            if (gj >= e.n) break;
+            const f32x4 w = *reinterpret_cast<const f32x4 *>(T + jj * TS + c4);
+            const float v[4] = {w[0], w[1], w[2], w[3]};
+            const int64_t idx = gj * e.ldk + m0 + c4;
+            if (e.vec_k) {
+                Store<OUT>::four(e.K, idx, v);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Store<OUT>::one(e.K, idx + r, v[r]);
+            }
+        }
+        __syncthreads();
+        // as is: T[ii][jj]
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) {
+                const int jj = wc * 64 + ni * 32 + l32;
+#pragma unroll
+                for (int rg = 0; rg < 4; ++rg) {
+                    const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) T[(ii0 + r) * TS + jj] = acc[mi][ni][4 * rg + r];
+                }
+            }
+        __syncthreads();
+        // K[m0 + ii][n0 .. n0 + 127]: every row exists; columns may pass n
+        for (int ii = tid >> 5; ii < GM; ii += GTHREADS / 32) {
+            const int64_t gj0 = n0 + c4;
+            if (gj0 >= e.n) continue;
+            const f32x4 w = *reinterpret_cast<const f32x4 *>(T + ii * TS + c4);
+            const float v[4] = {w[0], w[1], w[2], w[3]};
+            const int64_t idx = (m0 + ii) * e.ldk + gj0;
+            if (e.vec_k && gj0 + 3 < e.n) {
+                Store<OUT>::four(e.K, idx, v);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (gj0 + r < e.n) Store<OUT>::one(e.K, idx + r, v[r]);
+            }
+        }
+        __syncthreads();
+        return;
+    }
+    // diagonal tile: the upper triangle is the source of truth
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi) {
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni) {
             const int jj = wc * 64 + ni * 32 + l32;
             const int64_t gj = n0 + jj;
-            const bool jin = gj < e.n;
-            const float nrm_j = (e.kernel == KKM_GAUSS && jin) ? e.nrm[gj] : 0.f;
-            const float s_j = (e.scale && jin) ? e.scale[gj] : 1.f;
+            const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
 #pragma unroll
             for (int rg = 0; rg < 4; ++rg) {
                 const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
-                const int64_t gi0 = m0 + ii0;
-                float v[4], b[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int64_t gi = gi0 + r;
-                    const bool iin = gi < e.n;
-                    const float nrm_i = (e.kernel == KKM_GAUSS && iin) ? e.nrm[gi] : 0.f;
-                    b[r] = acc[mi][ni][4 * rg + r];
-                    if (e.scale) b[r] *= (iin ? e.scale[gi] : 1.f) * s_j;
-                    v[r] = kappa_from_dot(b[r], nrm_i, nrm_j, e.kernel, e.gamma, e.coef0,
-                                          e.degree);
-                }
-                if (!diag_tile) {
-                    // K[gi][gj]: the 32 lanes of a half write 32 consecutive entries of a row
-                    if (jin) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (gi0 + r < e.n) Store<OUT>::one(e.K, (gi0 + r) * e.ldk + gj, v[r]);
-                    }
-                    const f32x4 w = {v[0], v[1], v[2], v[3]};
-                    *reinterpret_cast<f32x4 *>(T + jj * TS + ii0) = w;
-                } else if (jin) {
-                    // diagonal tile: the upper triangle is the source of truth
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t gi = gi0 + r;
-                        if (gi >= e.n || gi > gj) continue;
-                        if (gi == gj) {
-                            // kappa(x, x) = exp(0) = 1 exactly; a non-finite row stays visible
-                            const float dv = (e.kernel == KKM_GAUSS)
-                                                 ? (isfinite(b[r]) ? 1.0f : __builtin_nanf(""))
-                                                 : Store<OUT>::round(v[r]);
-                            Store<OUT>::one(e.K, gi * e.ldk + gi, dv);
-                            e.diag[gi] = dv;
-                        } else {
-                            Store<OUT>::one(e.K, gi * e.ldk + gj, v[r]);
-                            Store<OUT>::one(e.K, gj * e.ldk + gi, v[r]);
-                        }
+                    const int64_t gi = m0 + ii0 + r;
+                    if (gj >= e.n || gi >= e.n || gi > gj) continue;
+                    float b = acc[mi][ni][4 * rg + r];
+                    if (e.scale) b *= rs[ii0 + r] * s_j;
+                    const float v = kappa_from_dot(b, rn[ii0 + r], nrm_j, e.kernel, e.gamma,
+                                                   e.coef0, e.degree);
+                    if (gi == gj) {
+                        // kappa(x, x) = exp(0) = 1 exactly; a non-finite row stays visible
+                        const float dv = (e.kernel == KKM_GAUSS)
+                                             ? (isfinite(b) ? 1.0f : __builtin_nanf(""))
+                                             : Store<OUT>::round(v);
+                        Store<OUT>::one(e.K, gi * e.ldk + gi, dv);
+                        e.diag[gi] = dv;
+                    } else {
+                        Store<OUT>::one(e.K, gi * e.ldk + gj, v);
+                        Store<OUT>::one(e.K, gj * e.ldk + gi, v);
                     }
                 }
             }
-        }
-    }
-    if (diag_tile) return;  // uniform across the workgroup
-    __syncthreads();
-    // K[n0 + jj][m0 .. m0 + 127]: 32 threads per row, 4 entries each, 8 rows per
-    // pass.  Off the diagonal m0 + 127 < n0 < n, so only the row needs a check.
-    const int tid = threadIdx.x;
-    const int c4 = (tid & 31) * 4;
-    for (int jj = tid >> 5; jj < GM; jj += GTHREADS / 32) {
-        const int64_t gj = n0 + jj;
-        if (gj >= e.n) break;
-        const f32x4 w = *reinterpret_cast<const f32x4 *>(T + jj * TS + c4);
-        const float v[4] = {w[0], w[1], w[2], w[3]};
-        const int64_t idx = gj * e.ldk + m0 + c4;
-        if (e.vec_k) {
-            Store<OUT>::four(e.K, idx, v);
-        } else {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Store<OUT>::one(e.K, idx + r, v[r]);
         }
     }
     __syncthreads();
@@ -231,7 +276,10 @@ struct F32Tile {
     Epi e;
 };
 
-typedef float F32Lds[2][2][GM * GLD];
+struct F32Lds {
+    float op[2][2][GM * GLD];  // operand slabs, double-buffered
+    float rn[2 * GM], rs[2 * GM];
+};
 
 __device__ __forceinline__ f32x4 load_row4(const F32Tile &a, int64_t row, int64_t col) {
     f32x4 v = {0.f, 0.f, 0.f, 0.f};
@@ -271,8 +319,8 @@ __device__ __forceinline__ void f32_tile(const F32Tile &a, int64_t bi, int64_t b
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            *reinterpret_cast<f32x4 *>(&lds[buf][0][(ld_row + 32 * u) * GLD + ld_col]) = ra[u];
-            *reinterpret_cast<f32x4 *>(&lds[buf][1][(ld_row + 32 * u) * GLD + ld_col]) = rb[u];
+            *reinterpret_cast<f32x4 *>(&lds.op[buf][0][(ld_row + 32 * u) * GLD + ld_col]) = ra[u];
+            *reinterpret_cast<f32x4 *>(&lds.op[buf][1][(ld_row + 32 * u) * GLD + ld_col]) = rb[u];
         }
     };
 
@@ -285,6 +333,7 @@ __device__ __forceinline__ void f32_tile(const F32Tile &a, int64_t bi, int64_t b
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     const int64_t nk = (a.d + GK - 1) / GK;
+    stage_norms(a.e, m0, n0, lds.rn, lds.rs);
     gload(0);
     sstore(0);
     __syncthreads();
@@ -298,8 +347,8 @@ __device__ __forceinline__ void f32_tile(const F32Tile &a, int64_t bi, int64_t b
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) gload((kt + 1) * GK);
-        const float *As = lds[buf][0];
-        const float *Bs = lds[buf][1];
+        const float *As = lds.op[buf][0];
+        const float *Bs = lds.op[buf][1];
         f32x4 av[2][4], bv[2][4];
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
@@ -322,8 +371,8 @@ __device__ __forceinline__ void f32_tile(const F32Tile &a, int64_t bi, int64_t b
         if (kt + 1 < nk) sstore(buf ^ 1);
         __syncthreads();
     }
-    static_assert(sizeof(F32Lds) >= EPI_LDS_BYTES, "epilogue tile does not fit");
-    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane, &lds[0][0][0]);
+    static_assert(sizeof(lds.op) >= EPI_LDS_BYTES, "epilogue tile does not fit");
+    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane, &lds.op[0][0][0], lds.rn, lds.rs);
 }
 
 // Squared norm of one FP32 row (Gaussian, FP32 product), by one whole wave.
@@ -349,7 +398,10 @@ struct LowpTile {
     Epi e;
 };
 
-typedef unsigned char LowpLds[2][2][GM * SLD];
+struct LowpLds {
+    unsigned char op[2][2][GM * SLD];  // operand slabs, double-buffered
+    float rn[2 * GM], rs[2 * GM];
+};
 
 // Row length of the rounded matrix: d rounded up to whole slabs.
 inline int64_t padded_d(int64_t d, int32_t gram_prec) {
@@ -386,8 +438,8 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            *reinterpret_cast<uint4 *>(&lds[buf][0][(ld_row + 32 * u) * SLD + ld_col]) = ra[u];
-            *reinterpret_cast<uint4 *>(&lds[buf][1][(ld_row + 32 * u) * SLD + ld_col]) = rb[u];
+            *reinterpret_cast<uint4 *>(&lds.op[buf][0][(ld_row + 32 * u) * SLD + ld_col]) = ra[u];
+            *reinterpret_cast<uint4 *>(&lds.op[buf][1][(ld_row + 32 * u) * SLD + ld_col]) = rb[u];
         }
     };
 
@@ -399,6 +451,7 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
+    stage_norms(a.e, m0, n0, lds.rn, lds.rs);
     gload(0);
     sstore(0);
     __syncthreads();
@@ -412,8 +465,8 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
     for (int64_t kt = 0; kt < a.nslab; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < a.nslab) gload(kt + 1);
-        const unsigned char *As = lds[buf][0];
-        const unsigned char *Bs = lds[buf][1];
+        const unsigned char *As = lds.op[buf][0];
+        const unsigned char *Bs = lds.op[buf][1];
         uint4 av[2][4], bv[2][4];
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
@@ -456,9 +509,9 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
         if (kt + 1 < a.nslab) sstore(buf ^ 1);
         __syncthreads();
     }
-    static_assert(sizeof(LowpLds) >= EPI_LDS_BYTES, "epilogue tile does not fit");
+    static_assert(sizeof(lds.op) >= EPI_LDS_BYTES, "epilogue tile does not fit");
     epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane,
-                  reinterpret_cast<float *>(&lds[0][0][0]));
+                  reinterpret_cast<float *>(&lds.op[0][0][0]), lds.rn, lds.rs);
 }
 
 __device__ __forceinline__ float wave_max(float v) {

@@ -83,18 +83,13 @@ int64_t inst_sweep_items(const InstGeom &g, int32_t k_store);
 // Sets the strip counts that depend on the element type of K.
 void inst_set_store(Inst *in, int32_t k_store);
 
-// The six kernels of one step over the whole set.  total_blocks and
-// total_clusters are grid sizes (sums over every problem the table can hold);
-// sweep_grid is the item count of a single problem, or for a table the size
-// of the persistent sweep grid; max_k sizes the dynamic LDS; vec: every K row
-// is 16-byte aligned.
+// The six kernels of one step over the whole set.  total_blocks,
+// total_clusters and sweep_grid are grid sizes: label blocks, clusters and
+// sweep items summed over every problem the set can hold; max_k sizes the
+// dynamic LDS; vec: every K row is 16-byte aligned.
 kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clusters,
                        int64_t sweep_grid, int32_t max_k, int32_t k_store, bool vec,
                        const int32_t *labels_in, int32_t *labels_out, hipStream_t stream);
-
-// Workgroups of the table-form sweep (K rows 16-byte aligned) that one compute
-// unit holds at once: the persistent sweep grid is this times the CU count.
-int sweep_blocks_per_cu(int32_t k_store);
 
 kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
                       int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,

@@ -35,6 +35,7 @@ namespace {
 
 constexpr int kPtsPerBlock = 256;          // points per block in the label kernels
 constexpr int kSweepThreads = 256;         // 4 waves
+constexpr int kSlotWindow = 1024;          // slot -> cluster entries per LDS window
 
 // The problem and the block index within it for a flattened grid position g;
 // false when g lies past the live problems of a table.  MULTI selects the
@@ -396,30 +397,18 @@ __device__ __forceinline__ void sweep_item(const Inst &in, int64_t item, const i
     }
 }
 
-// One problem: one workgroup per item.  A table: a persistent grid whose
-// workgroups take contiguous, equal ranges of the live problems' items (all
-// items cost the same), looking a problem up only when the range crosses into
-// the next one.
+// One workgroup per item.  For a table the grid covers the items of every
+// problem the table can hold and workgroups past the live total exit.  (A
+// persistent grid looping over contiguous item ranges measured 4.5% slower:
+// its loop raised the kernel from 64 to 76 VGPRs, 6 waves per SIMD instead of
+// 8.)
 template <typename T, bool VEC, bool MULTI>
 __global__ __launch_bounds__(kSweepThreads) void spmm_row_sweep(InstSet s,
                                                                 const int32_t *labels_all) {
-    if constexpr (!MULTI) {
-        sweep_item<T, VEC>(s.one, blockIdx.x, labels_all);
-    } else {
-        const int64_t total = uniform_load(s.item_start + s.count);
-        const int64_t g0 = total * blockIdx.x / gridDim.x;
-        const int64_t g1 = total * (blockIdx.x + 1) / gridDim.x;
-        int32_t b = 0;
-        int64_t lo = 0, hi = 0;  // item range of problem b
-        for (int64_t g = g0; g < g1; ++g) {
-            if (g >= hi) {
-                b = find_inst(s.item_start, s.count, g);
-                lo = uniform_load(s.item_start + b);
-                hi = uniform_load(s.item_start + b + 1);
-            }
-            sweep_item<T, VEC>(uniform_load(s.table + b), g - lo, labels_all);
-        }
-    }
+    Inst in;
+    int64_t item;
+    if (!locate<MULTI>(s, s.item_start, blockIdx.x, in, item)) return;
+    sweep_item<T, VEC>(in, item, labels_all);
 }
 
 // ---------------------------------------------------------------- 3. centroid norms
@@ -478,7 +467,7 @@ template <bool MULTI>
 __global__ __launch_bounds__(kPtsPerBlock) void assign_fused(InstSet s,
                                                              const int32_t *labels_in_all,
                                                              int32_t *labels_out_all) {
-    extern __shared__ int32_t sh[];  // off[k+1], hist[k]
+    extern __shared__ int32_t sh[];  // off[k+1], hist[k], seg[kSlotWindow]
     __shared__ double wJ[kPtsPerBlock / kWave];
     __shared__ long long wC[kPtsPerBlock / kWave];
     __shared__ bool last;
@@ -492,6 +481,7 @@ __global__ __launch_bounds__(kPtsPerBlock) void assign_fused(InstSet s,
     int32_t *__restrict__ labels_out = labels_out_all + in.lab_off;
     int32_t *off = sh;
     int32_t *hist = sh + (k + 1);
+    int32_t *seg = hist + k;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     if (*in.err != 0) {
@@ -507,37 +497,76 @@ __global__ __launch_bounds__(kPtsPerBlock) void assign_fused(InstSet s,
 
     const int64_t i = lb * kPtsPerBlock + tid;
     const bool valid = i < in.n;
+    const float dii = valid ? in.diag[i] : 0.f;
+    const int32_t a_in = valid ? labels_in[i] : -1;
+    float best = __builtin_inff();
+    int32_t arg = -1;
+    float own = 0.f;
+    auto visit = [&](int32_t c, float dic) {
+        if (in.D_out) in.D_out[i * k + c] = dic;
+        if (c == a_in) own = dic;
+        if (dic < best) {
+            best = dic;
+            arg = c;
+        }
+    };
+    const float empty_d = (in.empty_policy == KKM_EMPTY_ZERO_CENTROID) ? dii : __builtin_inff();
+    // S_ic of cluster `cur` is the compensated sum of its segments' partials, in
+    // CSR order; clusters without a segment are empty
+    int32_t cur = -1;
+    float sum = 0.f, comp = 0.f;
+    auto close = [&]() {
+        const float e = (sum + comp) / (float)(off[cur + 1] - off[cur]);
+        visit(cur, fmaf(-2.0f, e, dii) + in.ctilde[cur]);
+    };
+    // Segment (q, c) of the sweep sits in slot q + c; slots rise with CSR
+    // position.  A window of the slot -> cluster map is built in LDS, then each
+    // thread reads its column of the window's partials eight loads at a time.
+    const int64_t nslot = (in.n + L - 1) / L + k;
+    for (int64_t s0 = 0; s0 < nslot; s0 += kSlotWindow) {
+        const int w = (int)min((int64_t)kSlotWindow, nslot - s0);
+        for (int t = tid; t < w; t += kPtsPerBlock) seg[t] = -1;
+        __syncthreads();
+        for (int c = tid; c < k; c += kPtsPerBlock) {
+            const int64_t lo = off[c], hi = off[c + 1];
+            if (hi > lo) {
+                const int64_t a = max(lo / L + c, s0), b = min((hi - 1) / L + c, s0 + w - 1);
+                for (int64_t t = a; t <= b; ++t) seg[t - s0] = c;
+            }
+        }
+        __syncthreads();
+        if (valid) {
+            for (int t0 = 0; t0 < w; t0 += 8) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int32_t c = (t0 + u < w) ? seg[t0 + u] : -1;
+                    v[u] = (c >= 0) ? P[(s0 + t0 + u) * ldp + i] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int32_t c = (t0 + u < w) ? seg[t0 + u] : -1;
+                    if (c < 0) continue;
+                    if (c != cur) {
+                        if (cur >= 0) close();
+                        for (int32_t e = cur + 1; e < c; ++e) visit(e, empty_d);
+                        cur = c;
+                        sum = comp = 0.f;
+                    }
+                    float x, er;
+                    two_sum(sum, v[u], x, er);
+                    sum = x;
+                    comp += er;
+                }
+            }
+        }
+        __syncthreads();
+    }
     double own_d = 0.0;
     long long changed = 0;
     if (valid) {
-        const float dii = in.diag[i];
-        const int32_t a_in = labels_in[i];
-        float best = __builtin_inff();
-        int32_t arg = -1;
-        float own = 0.f;
-        for (int32_t c = 0; c < k; ++c) {
-            const int64_t lo = off[c], hi = off[c + 1];
-            float dic;
-            if (hi > lo) {
-                float sum = 0.f, comp = 0.f;
-                for (int64_t q = lo / L; q <= (hi - 1) / L; ++q) {
-                    float u, er;
-                    two_sum(sum, P[(q + c) * ldp + i], u, er);
-                    sum = u;
-                    comp += er;
-                }
-                const float e = (sum + comp) / (float)(hi - lo);
-                dic = fmaf(-2.0f, e, dii) + in.ctilde[c];
-            } else {
-                dic = (in.empty_policy == KKM_EMPTY_ZERO_CENTROID) ? dii : __builtin_inff();
-            }
-            if (in.D_out) in.D_out[i * k + c] = dic;
-            if (c == a_in) own = dic;
-            if (dic < best) {
-                best = dic;
-                arg = c;
-            }
-        }
+        if (cur >= 0) close();
+        for (int32_t e = cur + 1; e < k; ++e) visit(e, empty_d);
         if (arg < 0) arg = a_in;
         labels_out[i] = arg;
         atomicAdd(&hist[arg], 1);
@@ -696,23 +725,14 @@ kkm_status step_launch_t(const InstSet &s, int64_t total_blocks, int64_t total_c
         hipLaunchKernelGGL((centroid_norms<8, MULTI>), dim3((unsigned)total_clusters), dim3(256), 0, stream, s);
     KKM_HIP(hipGetLastError());
     hipLaunchKernelGGL(assign_fused<MULTI>, dim3((unsigned)total_blocks), pb,
-                       (size_t)(2 * max_k + 1) * sizeof(int32_t), stream, s, labels_in, labels_out);
+                       (size_t)(2 * max_k + 1 + kSlotWindow) * sizeof(int32_t), stream, s,
+                       labels_in, labels_out);
     KKM_HIP(hipGetLastError());
     timing_end(whole, stream);
     return KKM_OK;
 }
 
 }  // namespace
-
-int sweep_blocks_per_cu(int32_t k_store) {
-    int nb = 0;
-    hipError_t e = (k_store == KKM_F32)
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, spmm_row_sweep<float, true, true>, kSweepThreads, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, spmm_row_sweep<uint16_t, true, true>, kSweepThreads, 0);
-    return (e == hipSuccess && nb > 0) ? nb : 4;
-}
 
 kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clusters,
                        int64_t sweep_grid, int32_t max_k, int32_t k_store, bool vec,
