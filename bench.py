@@ -46,12 +46,12 @@ BF16_MFMA_PEAK_TFS = 2500.0
 # recorded value; otherwise the traffic is reported as null.
 TRAFFIC = {
     "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
-                       "sha256": "ad7eb214be00111fbc40297312c351c754586a69032f9ad3dc9f5054c7063be3",
-                       "n": 200000, "fetch_kib": 78170184.08, "write_kib": 84946.79,
+                       "sha256": "82b68ad40f6c8896156e91267981380c24f07740520d8327b9ec14472f2eec97",
+                       "n": 200000, "fetch_kib": 78169376.8, "write_kib": 85549.5,
                        "fetch_scale": 1.9999, "write_scale": 1.0},
     "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_tile.h", "csrc/kkm_common.h"],
-                      "sha256": "1d2d0a36aa3a5eb89125e6a1b3eb7da4d9cc78510b961bdfa065156d686e8c8c",
-                      "n": 200000, "fetch_kib": 317951206.94, "write_kib": 188456126.5,
+                      "sha256": "be9099a4a94dbd1dad73499dd12e336cb2c2bcc7f2f31bef1e912ce26f638edc",
+                      "n": 200000, "fetch_kib": 167039190.4, "write_kib": 156250901.8,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }
 
