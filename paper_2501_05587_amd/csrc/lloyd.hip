@@ -20,7 +20,7 @@ kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_
 
 namespace {
 
-constexpr int64_t kRows = 256;  // CSR positions per centroid-sum chunk
+constexpr int64_t kRows = 64;  // CSR positions per centroid-sum chunk
 
 struct LloydWs {
     int32_t *blk_hist, *blk_bad, *err, *counts, *perm, *offsets, *counts_out;
@@ -68,13 +68,17 @@ __global__ void feature_sqnorms(const float *F, int64_t n, int64_t f, int64_t ld
     if (lane == 0) fn[row] = s;
 }
 
-// grid (feature blocks of 256, chunks of kRows CSR positions)
+// One wave per (chunk of kRows CSR positions, block of 256 features): lane l
+// owns features 4l .. 4l+3 of the block; rows are read eight at a time and
+// summed per cluster segment, flushed to slot chunk + cluster.
 __global__ __launch_bounds__(256) void centroid_partials(const float *F, int64_t n, int64_t f,
-                                                         int64_t ldf, int32_t k,
+                                                         int64_t ldf, int32_t k, int64_t nchunk,
                                                          const int32_t *perm,
                                                          const int32_t *offsets, float *Cp) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t q = blockIdx.y;
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nchunk) return;
+    const int64_t t0 = (int64_t)blockIdx.y * 256 + (threadIdx.x & 63) * 4;
+    const bool vec = ((ldf & 3) == 0) && ((reinterpret_cast<uintptr_t>(F) & 15) == 0) && (t0 + 3 < f);
     const int64_t p0 = q * kRows, p1 = min(n, p0 + kRows);
     int32_t lo = 0, hi = k - 1;
     while (lo < hi) {
@@ -84,15 +88,38 @@ __global__ __launch_bounds__(256) void centroid_partials(const float *F, int64_t
     }
     int32_t c = lo;
     int64_t p = p0;
+    auto row = [&](int64_t j, float (&v)[4]) {
+        const float *x = F + j * ldf + t0;
+        if (vec) {
+            const f32x4 w = *reinterpret_cast<const f32x4 *>(x);
+            v[0] = w[0], v[1] = w[1], v[2] = w[2], v[3] = w[3];
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = (t0 + u < f) ? x[u] : 0.f;
+        }
+    };
     while (p < p1) {
         while (offsets[c + 1] <= p) ++c;
         const int64_t e = min(p1, (int64_t)offsets[c + 1]);
-        float s = 0.f;
-        for (; p < e; ++p) {
-            const int64_t j = __builtin_amdgcn_readfirstlane(perm[p]);
-            if (t < f) s += F[j * ldf + t];
+        float s[4] = {0.f, 0.f, 0.f, 0.f};
+        for (; p + 8 <= e; p += 8) {
+            float v[8][4];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) row(__builtin_amdgcn_readfirstlane(perm[p + r]), v[r]);
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) s[u] += v[r][u];
         }
-        if (t < f) Cp[(q + c) * f + t] = s;
+        for (; p < e; ++p) {
+            float v[4];
+            row(__builtin_amdgcn_readfirstlane(perm[p]), v);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s[u] += v[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t0 + u < f) Cp[(q + c) * f + t0 + u] = s[u];
     }
 }
 
@@ -122,10 +149,11 @@ __global__ __launch_bounds__(256) void centroid_finalize(const float *Cp, int64_
     if (threadIdx.x == 0) cn[c] = sh[0];
 }
 
+// Gt = C F^T ([k][n]: consecutive threads read consecutive entries).
 // Also writes, per block, the sum of the chosen (smallest) distances in FP64
 // (part, nullable): summed over blocks it is sum_i min_c d_ic, which equals the
 // objective of the new labels once no label changes.
-__global__ __launch_bounds__(256) void feature_assign(const float *G, const float *fn,
+__global__ __launch_bounds__(256) void feature_assign(const float *Gt, const float *fn,
                                                       const float *cn, const int32_t *offsets,
                                                       int64_t n, int32_t k,
                                                       const int32_t *labels_in,
@@ -141,7 +169,7 @@ __global__ __launch_bounds__(256) void feature_assign(const float *G, const floa
         int32_t arg = labels_in[i];
         for (int32_t c = 0; c < k; ++c) {
             if (offsets[c + 1] == offsets[c]) continue;
-            const float d = fmaf(-2.0f, G[i * k + c], fn[i]) + cn[c];
+            const float d = fmaf(-2.0f, Gt[(int64_t)c * n + i], fn[i]) + cn[c];
             if (d < best) {
                 best = d;
                 arg = c;
@@ -214,45 +242,51 @@ __global__ __launch_bounds__(256) void kpp_update(const float *F, int64_t n, int
     if (threadIdx.x == 0) bsum[blockIdx.x] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
 }
 
-// One workgroup: picks seed t+1 from the block sums and dmin.
+// One workgroup: picks seed t+1 from the block sums and dmin.  Thread r sums
+// its range of block sums; a block scan of the range sums locates the range
+// that holds u * total, and that range's thread walks its block sums and rows.
 __global__ __launch_bounds__(1024) void kpp_select(const double *bsum, int64_t nb, const float *dmin,
                                                    int64_t n, double u, int32_t *seeds, int t) {
-    __shared__ double part[1024];
-    __shared__ int64_t hit;
+    __shared__ double scan[2][1024];
     const int tid = threadIdx.x;
     const int64_t per = (nb + 1023) / 1024;
-    const int64_t b0 = (int64_t)tid * per, b1 = min(nb, b0 + per);
+    const int64_t b0 = min(nb, (int64_t)tid * per), b1 = min(nb, b0 + per);
     double s = 0.0;
     for (int64_t b = b0; b < b1; ++b) s += bsum[b];
-    part[tid] = s;
+    int cur = 0;
+    scan[0][tid] = s;
     __syncthreads();
-    if (tid == 0) {
-        double total = 0.0;
-        for (int i = 0; i < 1024; ++i) total += part[i];
-        int64_t pick = -1;
-        if (total > 0.0) {
-            const double target = u * total;
-            double run = 0.0;
-            int i = 0;
-            while (i < 1023 && run + part[i] <= target) run += part[i++];
-            int64_t b = (int64_t)i * per;
-            const int64_t bend = min(nb, b + per);
-            while (b < bend - 1 && run + bsum[b] <= target) run += bsum[b++];
-            for (int64_t r = b * kKppRows; r < min(n, (b + 1) * kKppRows); ++r) {
-                run += (double)dmin[r];
-                if (run > target) {
-                    pick = r;
-                    break;
-                }
-            }
-            if (pick < 0) pick = min(n, (b + 1) * kKppRows) - 1;  // rounding at the very end
-        } else {
-            pick = min((int64_t)(u * (double)n), n - 1);  // all rows coincide with seeds
-        }
-        hit = pick;
+    for (int off = 1; off < 1024; off <<= 1) {
+        const double v = scan[cur][tid] + ((tid >= off) ? scan[cur][tid - off] : 0.0);
+        scan[cur ^ 1][tid] = v;
+        cur ^= 1;
+        __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) seeds[t + 1] = (int32_t)hit;
+    const double total = scan[cur][1023];
+    const double incl = scan[cur][tid];
+    const double excl = (tid > 0) ? scan[cur][tid - 1] : 0.0;
+    if (!(total > 0.0)) {
+        if (tid == 0) seeds[t + 1] = (int32_t)min((int64_t)(u * (double)n), n - 1);
+        return;  // every row coincides with a seed
+    }
+    const double target = u * total;
+    // the first range whose inclusive sum passes the target (the last one if
+    // rounding leaves the target at the very end)
+    const bool mine = (incl > target && excl <= target) || (tid == 1023 && incl <= target);
+    if (!mine) return;
+    double run = excl;
+    int64_t b = b0;
+    while (b < b1 - 1 && run + bsum[b] <= target) run += bsum[b++];
+    int64_t pick = -1;
+    for (int64_t r = b * kKppRows; r < min(n, (b + 1) * kKppRows); ++r) {
+        run += (double)dmin[r];
+        if (run > target) {
+            pick = r;
+            break;
+        }
+    }
+    if (pick < 0) pick = min(n, (b + 1) * kKppRows) - 1;
+    seeds[t + 1] = (int32_t)pick;
 }
 
 __global__ void gather_seed_rows(const float *F, int64_t ldf, int64_t f, const int32_t *seeds,
@@ -293,7 +327,7 @@ extern "C" size_t kkm_feature_kmeanspp_workspace_bytes(int64_t n, int64_t f, int
     c.take<float>((size_t)(k * f));                            // seed rows
     c.take<float>((size_t)k);                                  // their norms
     c.take<float>((size_t)n);                                  // row norms
-    c.take<float>((size_t)(n * k));                            // F S^T
+    c.take<float>((size_t)(n * k));                            // S F^T
     c.take<int32_t>((size_t)k + 1);                            // offsets 0..k
     c.take<int32_t>((size_t)n);                                // placeholder input labels
     c.take<int64_t>(1);                                        // changed count
@@ -350,16 +384,16 @@ extern "C" kkm_status kkm_feature_kmeanspp(const float *F, int64_t n, int64_t f,
     hipLaunchKernelGGL(iota_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, lab_in, n);
     KKM_HIP(hipGetLastError());
     GemmArgs g{};
-    g.A = F;
-    g.lda = ldf;
-    g.B = C;
-    g.ldb = f;
-    g.M = n;
-    g.N = k;
+    g.A = C;
+    g.lda = f;
+    g.B = F;
+    g.ldb = ldf;
+    g.M = k;
+    g.N = n;
     g.K = f;
     g.alpha = 1.0f;
     g.C = G;
-    g.ldc = k;
+    g.ldc = n;
     KKM_TRY(gemm_launch(GEMM_F32, true, true, EPI_STORE, g, s));
     hipLaunchKernelGGL(feature_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, fn,
                        cn, offs, n, k, lab_in, labels_out, changed, nullptr);
@@ -416,22 +450,22 @@ extern "C" kkm_status kkm_feature_lloyd(const float *F, int64_t n, int64_t f, in
                 return KKM_ERR_LABEL;
             }
         }
-        hipLaunchKernelGGL(centroid_partials, dim3((unsigned)((f + 255) / 256), (unsigned)nchunk),
-                           dim3(256), 0, s, F, n, f, ldf, k, w.perm, w.offsets, w.Cp);
+        hipLaunchKernelGGL(centroid_partials, dim3((unsigned)((nchunk + 3) / 4), (unsigned)((f + 255) / 256)),
+                           dim3(256), 0, s, F, n, f, ldf, k, nchunk, w.perm, w.offsets, w.Cp);
         hipLaunchKernelGGL(centroid_finalize, dim3((unsigned)k), dim3(256), 0, s, w.Cp, f, k,
                            w.offsets, w.C, w.cn);
         KKM_HIP(hipGetLastError());
         GemmArgs g{};
-        g.A = F;
-        g.lda = ldf;
-        g.B = w.C;
-        g.ldb = f;
-        g.M = n;
-        g.N = k;
+        g.A = w.C;
+        g.lda = f;
+        g.B = F;
+        g.ldb = ldf;
+        g.M = k;
+        g.N = n;
         g.K = f;
         g.alpha = 1.0f;
         g.C = w.G;
-        g.ldc = k;
+        g.ldc = n;
         KKM_TRY(gemm_launch(GEMM_F32, true, true, EPI_STORE, g, s));
         hipLaunchKernelGGL(feature_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.G,
                            w.fn, w.cn, w.offsets, n, k, w.lab[cur], w.lab[cur ^ 1], w.changed,
