@@ -172,6 +172,24 @@ kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t
                       void *K_ws, int64_t ldk, double *J_trace, int64_t *changed_trace,
                       double *times_ms, void *stream);
 
+/*
+ * kkm_refine — the loop of kkm_fit_ex on a kernel matrix already in memory
+ * (Algorithm 2 without its first step): for warm starts that need K before
+ * the first step, such as kkm_kernel_kmeanspp.
+ *
+ *   K, k_store, ldk, diagK   as kkm_iterate (from kkm_gram).
+ *   empty_policy, labels0, max_iter, check_convergence, labels_out,
+ *   objective, iters, J_trace, changed_trace   as kkm_fit_ex.
+ *   times_ms   host double [2], nullable: {all steps, final objective pass}.
+ * Synchronises the stream before returning; the same labels0 give bitwise
+ * the same results as the loop inside kkm_fit_ex on the same K.
+ */
+kkm_status kkm_refine(const void *K, int32_t k_store, int64_t ldk, const float *diagK, int64_t n,
+                      int32_t k, int32_t empty_policy, const int32_t *labels0, int32_t max_iter,
+                      int32_t check_convergence, int32_t *labels_out, double *objective,
+                      int32_t *iters, double *J_trace, int64_t *changed_trace, double *times_ms,
+                      void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: many independent clustering problems of uneven sizes, each
  * the computation of kkm_fit_ex (Algorithm 2 of the paper run once per
@@ -329,6 +347,20 @@ kkm_status kkm_feature_kmeanspp(const float *F, int64_t n, int64_t f, int64_t ld
                                 const double *uniforms, int32_t *seeds, int32_t *labels_out,
                                 void *ws, size_t ws_bytes, void *stream);
 size_t kkm_feature_kmeanspp_workspace_bytes(int64_t n, int64_t f, int32_t k);
+
+/* K-means++ seeding in the kernel's feature space, from the kernel matrix
+ * itself (no learned features): the same D^2 sampling as
+ * kkm_feature_kmeanspp with the squared distance of point i to seed s taken
+ * as K_ii + K_ss - 2 K_si (Sec. 2.2's kernel trick on two points, clamped at
+ * 0 against rounding; FP32).  Reads one row of K per seed and k rows for the
+ * labels.  K [n, ldk] (KKM_F32 or KKM_BF16, k_store), diagK [n] as written by
+ * kkm_gram; uniforms: host double [k] in [0, 1); seeds (device int32 [k]);
+ * labels_out (device int32 [n]) = index of each point's nearest seed (lowest
+ * on ties).  k <= KKM_MAX_K.  Asynchronous. */
+kkm_status kkm_kernel_kmeanspp(const void *K, int32_t k_store, int64_t ldk, const float *diagK,
+                               int64_t n, int32_t k, const double *uniforms, int32_t *seeds,
+                               int32_t *labels_out, void *ws, size_t ws_bytes, void *stream);
+size_t kkm_kernel_kmeanspp_workspace_bytes(int64_t n, int32_t k);
 
 /*
  * Launch timing for benchmarks (process-wide).  kkm_timing_enable(1) clears

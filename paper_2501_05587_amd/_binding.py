@@ -29,6 +29,7 @@ EXPORTS = ("kkm_gram", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_w
            "kkm_feature_kmeanspp", "kkm_feature_kmeanspp_workspace_bytes",
            "kkm_mlp_train_fresh", "kkm_mlp_train_fresh_workspace_bytes",
            "kkm_fit_batched", "kkm_fit_batched_workspace_bytes",
+           "kkm_kernel_kmeanspp", "kkm_kernel_kmeanspp_workspace_bytes", "kkm_refine",
            "kkm_timing_enable", "kkm_timing_read", "kkm_last_error")
 
 
@@ -108,6 +109,14 @@ def lib():
         L.kkm_feature_kmeanspp_workspace_bytes.argtypes = [_i64, _i64, _i32]
         L.kkm_feature_kmeanspp.restype = ctypes.c_int
         L.kkm_feature_kmeanspp.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.kkm_refine.restype = ctypes.c_int
+        L.kkm_refine.argtypes = [_vp, _i32, _i64, _vp, _i64, _i32, _i32, _vp, _i32, _i32, _vp,
+                                 ctypes.POINTER(_d), ctypes.POINTER(_i32), _vp, _vp, _vp, _vp]
+        L.kkm_kernel_kmeanspp_workspace_bytes.restype = _sz
+        L.kkm_kernel_kmeanspp_workspace_bytes.argtypes = [_i64, _i32]
+        L.kkm_kernel_kmeanspp.restype = ctypes.c_int
+        L.kkm_kernel_kmeanspp.argtypes = [_vp, _i32, _i64, _vp, _i64, _i32, _vp, _vp, _vp, _vp,
+                                          _sz, _vp]
         L.kkm_fit_batched_workspace_bytes.restype = _sz
         L.kkm_fit_batched_workspace_bytes.argtypes = [ctypes.POINTER(KkmInstance), _i32, _i32, _i32]
         L.kkm_fit_batched.restype = ctypes.c_int
@@ -275,6 +284,62 @@ def kkm_fit_ex(X, k, labels0, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram
     t = int(it.value)
     return dict(labels=labels_out, objective=J.value, iters=t, J_trace=Jt[:t + 1],
                 changed_trace=Ct[:t], times_ms=tm)
+
+
+def kkm_refine(K, diagK, k, labels0, empty_policy=EMPTY_INF, max_iter=30, check_convergence=True,
+               labels_out=None):
+    """The loop of kkm_fit_ex on a resident K (float32 or bfloat16) and its
+    diagonal.  Returns a dict with labels, objective, iters, J_trace,
+    changed_trace and times_ms (steps, final objective pass)."""
+    import numpy as np
+    if not (isinstance(K, torch.Tensor) and K.is_cuda and K.dim() == 2):
+        raise TypeError("K must be a 2-d GPU tensor")
+    k_store = BF16 if K.dtype == torch.bfloat16 else F32
+    _dev(K, _kstore_dtype(k_store), "K", 2)
+    n, _, ldk = _rows(K, "K")
+    _dev(diagK, torch.float32, "diagK", 1)
+    _dev(labels0, torch.int32, "labels0", 1)
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=K.device)
+    J = _d()
+    it = _i32()
+    Jt = np.zeros(max_iter + 1, dtype=np.float64)
+    Ct = np.zeros(max(max_iter, 1), dtype=np.int64)
+    tm = np.zeros(2, dtype=np.float64)
+    _check(lib().kkm_refine(_ptr(K), k_store, ldk, _ptr(diagK), n, k, empty_policy, _ptr(labels0),
+                            max_iter, int(bool(check_convergence)), _ptr(labels_out),
+                            ctypes.byref(J), ctypes.byref(it), Jt.ctypes.data_as(_vp),
+                            Ct.ctypes.data_as(_vp), tm.ctypes.data_as(_vp), _stream()))
+    t = int(it.value)
+    return dict(labels=labels_out, objective=J.value, iters=t, J_trace=Jt[:t + 1],
+                changed_trace=Ct[:t], times_ms=tm)
+
+
+def kkm_kernel_kmeanspp(K, diagK, k, uniforms, seeds=None, labels_out=None, ws=None):
+    """K-means++ seeds in the kernel's feature space from the kernel matrix K
+    (float32 or bfloat16, as kkm_gram writes it) and its diagonal.
+    Returns (seeds, labels_out): device int32 [k] and [n]."""
+    import numpy as np
+    if not (isinstance(K, torch.Tensor) and K.is_cuda and K.dim() == 2):
+        raise TypeError("K must be a 2-d GPU tensor")
+    k_store = BF16 if K.dtype == torch.bfloat16 else F32
+    _dev(K, _kstore_dtype(k_store), "K", 2)
+    n, _, ldk = _rows(K, "K")
+    _dev(diagK, torch.float32, "diagK", 1)
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    if u.shape != (k,):
+        raise ValueError("need k uniforms")
+    if seeds is None:
+        seeds = torch.empty(k, dtype=torch.int32, device=K.device)
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=K.device)
+    need = int(lib().kkm_kernel_kmeanspp_workspace_bytes(n, k))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=K.device)
+    _check(lib().kkm_kernel_kmeanspp(_ptr(K), k_store, ldk, _ptr(diagK), n, k,
+                                     u.ctypes.data_as(_vp), _ptr(seeds), _ptr(labels_out),
+                                     _ptr(ws), ws.numel(), _stream()))
+    return seeds, labels_out
 
 
 def _instances(problems):

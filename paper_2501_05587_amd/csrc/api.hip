@@ -250,6 +250,125 @@ extern "C" kkm_status kkm_iterate(const void *K, int32_t k_store, int64_t ldk,
                           (hipStream_t)stream);
 }
 
+namespace kkm {
+namespace {
+
+// The loop of Algorithm 2 on a resident K: steps from labels0 until no label
+// changes (check_convergence) or max_iter steps, then the objective of the
+// final labels (free when the last step changed nothing).  times_ms (host
+// double[2], nullable): {all steps, final objective pass}.
+kkm_status run_loop(const void *K, int32_t k_store, int64_t ldk, const float *diag, int64_t n,
+                    int32_t k, int32_t empty_policy, const int32_t *labels0, int32_t max_iter,
+                    int32_t check_convergence, int32_t *labels_out, double *objective,
+                    int32_t *iters, double *J_trace, int64_t *changed_trace, double *times_ms,
+                    const char *who, hipStream_t s) {
+    const int32_t steps_cap = max_iter + 1;
+    const size_t iws = iterate_workspace_bytes(n, k);
+    FitBuffers fb;
+    Carver c(nullptr);
+    c.take<char>(iws);
+    c.take<int32_t>((size_t)n);           // labels A
+    c.take<int32_t>((size_t)n);           // labels B
+    c.take<int32_t>((size_t)k);           // counts
+    c.take<int64_t>((size_t)steps_cap);   // changed per step
+    c.take<double>((size_t)steps_cap);    // J per step
+    KKM_HIP(hipMalloc(&fb.block, c.bytes()));
+    Carver w(fb.block);
+    void *iter_ws = w.take<char>(iws);
+    int32_t *lab[2] = {w.take<int32_t>((size_t)n), w.take<int32_t>((size_t)n)};
+    int32_t *counts = w.take<int32_t>((size_t)k);
+    int64_t *changed_dev = w.take<int64_t>((size_t)steps_cap);
+    double *J_dev = w.take<double>((size_t)steps_cap);
+    KKM_HIP(hipHostMalloc((void **)&fb.host, sizeof(double) * 4, hipHostMallocDefault));
+
+    hipEvent_t ev[3];
+    for (auto &e : ev) KKM_HIP(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int i = 0; i < 3; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } evg{ev};
+
+    KKM_HIP(hipMemcpyAsync(lab[0], labels0, (size_t)n * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, s));
+    KKM_HIP(hipEventRecord(ev[0], s));
+    int cur = 0;
+    int32_t t = 0;
+    int64_t last_changed = -1;
+    int64_t *hchanged = reinterpret_cast<int64_t *>(fb.host + 1);
+    for (; t < max_iter; ++t) {
+        KKM_TRY(iterate_launch(K, k_store, ldk, diag, n, k, lab[cur], empty_policy, lab[cur ^ 1],
+                               counts, changed_dev + t, J_dev + t, nullptr, nullptr, iter_ws, iws,
+                               s));
+        if (check_convergence || t == 0) {
+            KKM_HIP(hipMemcpyAsync(hchanged, changed_dev + t, sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, s));
+            KKM_HIP(hipStreamSynchronize(s));
+            if (*hchanged < 0) {
+                set_error("%s: a label of labels0 lies outside [0, %d)", who, k);
+                return KKM_ERR_LABEL;
+            }
+        }
+        cur ^= 1;
+        if (check_convergence && *hchanged == 0) {
+            last_changed = 0;
+            ++t;
+            break;
+        }
+    }
+    KKM_HIP(hipEventRecord(ev[1], s));
+    // objective of the final labels: free after a step that changed nothing
+    const bool need_final = !(t > 0 && last_changed == 0);
+    if (need_final) {
+        KKM_TRY(iterate_launch(K, k_store, ldk, diag, n, k, lab[cur], empty_policy, lab[cur ^ 1],
+                               counts, changed_dev + t, J_dev + t, nullptr, nullptr, iter_ws, iws,
+                               s));
+    }
+    KKM_HIP(hipEventRecord(ev[2], s));
+    KKM_HIP(hipMemcpyAsync(labels_out, lab[cur], (size_t)n * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, s));
+    KKM_HIP(hipStreamSynchronize(s));
+
+    // per-step records
+    int64_t *hc = new int64_t[(size_t)steps_cap];
+    double *hj = new double[(size_t)steps_cap];
+    hipError_t e1 = hipMemcpy(hc, changed_dev, sizeof(int64_t) * (size_t)(t + 1),
+                              hipMemcpyDeviceToHost);
+    hipError_t e2 = hipMemcpy(hj, J_dev, sizeof(double) * (size_t)(t + 1), hipMemcpyDeviceToHost);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        delete[] hc;
+        delete[] hj;
+        return hip_fail(e1 != hipSuccess ? e1 : e2, "hipMemcpy(step records)");
+    }
+    if (!need_final) hj[t] = hj[t - 1];  // the no-change step's input labels are the final ones
+    kkm_status st = KKM_OK;
+    if (hc[need_final ? t : 0] < 0) {
+        set_error("%s: a label of labels0 lies outside [0, %d)", who, k);
+        st = KKM_ERR_LABEL;
+    } else {
+        *objective = hj[t];
+        *iters = t;
+        if (J_trace)
+            for (int32_t u = 0; u <= t; ++u) J_trace[u] = hj[u];
+        if (changed_trace)
+            for (int32_t u = 0; u < t; ++u) changed_trace[u] = hc[u];
+        if (times_ms) {
+            float a = 0.f, b = 0.f;
+            (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+            (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+            times_ms[0] = a;
+            times_ms[1] = b;
+        }
+    }
+    delete[] hc;
+    delete[] hj;
+    return st;
+}
+
+}  // namespace
+}  // namespace kkm
+
 extern "C" kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t k,
                                  int32_t kernel_type, double gamma, double coef0,
                                  int32_t degree, int32_t gram_prec, int32_t k_store,
@@ -294,37 +413,24 @@ extern "C" kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t l
         }
         K = fb.K_own;
     }
-    const int32_t steps_cap = max_iter + 1;
     const size_t gws = gram_workspace_bytes(n, d, gram_prec);
-    const size_t iws = iterate_workspace_bytes(n, k);
     Carver c(nullptr);
     c.take<char>(gws);
-    c.take<char>(iws);
-    c.take<float>((size_t)n);             // diag
-    c.take<int32_t>((size_t)n);           // labels A
-    c.take<int32_t>((size_t)n);           // labels B
-    c.take<int32_t>((size_t)k);           // counts
-    c.take<int64_t>((size_t)steps_cap);   // changed per step
-    c.take<double>((size_t)steps_cap);    // J per step
-    c.take<int32_t>(1);                   // non-finite flag
+    c.take<float>((size_t)n);   // diag
+    c.take<int32_t>(1);         // non-finite flag
     KKM_HIP(hipMalloc(&fb.block, c.bytes()));
     Carver w(fb.block);
     void *gram_ws = w.take<char>(gws);
-    void *iter_ws = w.take<char>(iws);
     float *diag = w.take<float>((size_t)n);
-    int32_t *lab[2] = {w.take<int32_t>((size_t)n), w.take<int32_t>((size_t)n)};
-    int32_t *counts = w.take<int32_t>((size_t)k);
-    int64_t *changed_dev = w.take<int64_t>((size_t)steps_cap);
-    double *J_dev = w.take<double>((size_t)steps_cap);
     int32_t *flag = w.take<int32_t>(1);
-    KKM_HIP(hipHostMalloc((void **)&fb.host, sizeof(double) * 4, hipHostMallocDefault));
+    KKM_HIP(hipHostMalloc((void **)&fb.host, sizeof(double) * 2, hipHostMallocDefault));
 
-    hipEvent_t ev[4];
+    hipEvent_t ev[2];
     for (auto &e : ev) KKM_HIP(hipEventCreate(&e));
     struct EvGuard {
         hipEvent_t *e;
         ~EvGuard() {
-            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+            for (int i = 0; i < 2; ++i) (void)hipEventDestroy(e[i]);
         }
     } evg{ev};
 
@@ -334,8 +440,6 @@ extern "C" kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t l
     flag_nonfinite(diag, n, flag, s);
     KKM_HIP(hipGetLastError());
     KKM_HIP(hipEventRecord(ev[1], s));
-    KKM_HIP(hipMemcpyAsync(lab[0], labels0, (size_t)n * sizeof(int32_t),
-                           hipMemcpyDeviceToDevice, s));
     int32_t *hflag = reinterpret_cast<int32_t *>(fb.host);
     KKM_HIP(hipMemcpyAsync(hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     KKM_HIP(hipStreamSynchronize(s));
@@ -343,80 +447,48 @@ extern "C" kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t l
         set_error("kkm_fit: diag(K) has a non-finite entry (NaN or infinity in X?)");
         return KKM_ERR_NONFINITE;
     }
+    double loop_ms[2] = {0.0, 0.0};
+    KKM_TRY(run_loop(K, k_store, ldk, diag, n, k, empty_policy, labels0, max_iter,
+                     check_convergence, labels_out, objective, iters, J_trace, changed_trace,
+                     loop_ms, "kkm_fit", s));
+    if (times_ms) {
+        float a = 0.f;
+        (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+        times_ms[0] = a;
+        times_ms[1] = loop_ms[0];
+        times_ms[2] = loop_ms[1];
+    }
+    return KKM_OK;
+}
 
-    int cur = 0;
-    int32_t t = 0;
-    int64_t last_changed = -1;
-    int64_t *hchanged = reinterpret_cast<int64_t *>(fb.host + 1);
-    for (; t < max_iter; ++t) {
-        KKM_TRY(iterate_launch(K, k_store, ldk, diag, n, k, lab[cur], empty_policy, lab[cur ^ 1],
-                               counts, changed_dev + t, J_dev + t, nullptr, nullptr, iter_ws, iws,
-                               s));
-        if (check_convergence || t == 0) {
-            KKM_HIP(hipMemcpyAsync(hchanged, changed_dev + t, sizeof(int64_t),
-                                   hipMemcpyDeviceToHost, s));
-            KKM_HIP(hipStreamSynchronize(s));
-            if (*hchanged < 0) {
-                set_error("kkm_fit: a label of labels0 lies outside [0, %d)", k);
-                return KKM_ERR_LABEL;
-            }
-        }
-        cur ^= 1;
-        if (check_convergence && *hchanged == 0) {
-            last_changed = 0;
-            ++t;
-            break;
-        }
+extern "C" kkm_status kkm_refine(const void *K, int32_t k_store, int64_t ldk, const float *diagK,
+                                 int64_t n, int32_t k, int32_t empty_policy,
+                                 const int32_t *labels0, int32_t max_iter,
+                                 int32_t check_convergence, int32_t *labels_out,
+                                 double *objective, int32_t *iters, double *J_trace,
+                                 int64_t *changed_trace, double *times_ms, void *stream) {
+    g_err[0] = 0;
+    if (n < 1 || k < 1 || k > n || ldk < n || max_iter < 0 || !K || !diagK || !labels0 ||
+        !labels_out || !objective || !iters) {
+        set_error("kkm_refine: bad sizes or NULL pointer (n=%lld k=%d ldk=%lld max_iter=%d)",
+                  (long long)n, k, (long long)ldk, max_iter);
+        return KKM_ERR_ARG;
     }
-    KKM_HIP(hipEventRecord(ev[2], s));
-    // objective of the final labels: free after a step that changed nothing
-    bool need_final = !(t > 0 && last_changed == 0);
-    if (need_final) {
-        KKM_TRY(iterate_launch(K, k_store, ldk, diag, n, k, lab[cur], empty_policy, lab[cur ^ 1],
-                               counts, changed_dev + t, J_dev + t, nullptr, nullptr, iter_ws, iws,
-                               s));
+    if (k > KKM_MAX_K) {
+        set_error("kkm_refine: k=%d exceeds KKM_MAX_K=%d", k, KKM_MAX_K);
+        return KKM_ERR_UNSUPPORTED;
     }
-    KKM_HIP(hipEventRecord(ev[3], s));
-    KKM_HIP(hipMemcpyAsync(labels_out, lab[cur], (size_t)n * sizeof(int32_t),
-                           hipMemcpyDeviceToDevice, s));
-    KKM_HIP(hipStreamSynchronize(s));
-
-    // per-step records
-    int64_t *hc = new int64_t[(size_t)steps_cap];
-    double *hj = new double[(size_t)steps_cap];
-    hipError_t e1 = hipMemcpy(hc, changed_dev, sizeof(int64_t) * (size_t)(t + 1),
-                              hipMemcpyDeviceToHost);
-    hipError_t e2 = hipMemcpy(hj, J_dev, sizeof(double) * (size_t)(t + 1), hipMemcpyDeviceToHost);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
-        delete[] hc;
-        delete[] hj;
-        return hip_fail(e1 != hipSuccess ? e1 : e2, "hipMemcpy(step records)");
+    if (k_store != KKM_F32 && k_store != KKM_BF16) {
+        set_error("kkm_refine: K must be stored as KKM_F32 or KKM_BF16");
+        return KKM_ERR_ARG;
     }
-    if (!need_final) hj[t] = hj[t - 1];  // the no-change step's input labels are the final ones
-    kkm_status st = KKM_OK;
-    if (hc[need_final ? t : 0] < 0) {
-        set_error("kkm_fit: a label of labels0 lies outside [0, %d)", k);
-        st = KKM_ERR_LABEL;
-    } else {
-        *objective = hj[t];
-        *iters = t;
-        if (J_trace)
-            for (int32_t u = 0; u <= t; ++u) J_trace[u] = hj[u];
-        if (changed_trace)
-            for (int32_t u = 0; u < t; ++u) changed_trace[u] = hc[u];
-        if (times_ms) {
-            float a = 0.f, b = 0.f, cc = 0.f;
-            (void)hipEventElapsedTime(&a, ev[0], ev[1]);
-            (void)hipEventElapsedTime(&b, ev[1], ev[2]);
-            (void)hipEventElapsedTime(&cc, ev[2], ev[3]);
-            times_ms[0] = a;
-            times_ms[1] = b;
-            times_ms[2] = cc;
-        }
+    if (empty_policy != KKM_EMPTY_INF && empty_policy != KKM_EMPTY_ZERO_CENTROID) {
+        set_error("kkm_refine: unknown empty-cluster policy %d", empty_policy);
+        return KKM_ERR_ARG;
     }
-    delete[] hc;
-    delete[] hj;
-    return st;
+    return run_loop(K, k_store, ldk, diagK, n, k, empty_policy, labels0, max_iter,
+                    check_convergence, labels_out, objective, iters, J_trace, changed_trace,
+                    times_ms, "kkm_refine", (hipStream_t)stream);
 }
 
 extern "C" kkm_status kkm_fit(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t k,

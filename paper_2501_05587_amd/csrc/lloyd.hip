@@ -289,6 +289,63 @@ __global__ __launch_bounds__(1024) void kpp_select(const double *bsum, int64_t n
     seeds[t + 1] = (int32_t)pick;
 }
 
+// ---------------------------------------------------------------- seeding on K
+//
+// The same D^2 sampling in the kernel's feature space, with no features: the
+// squared distance of point i to seed s is K_ii + K_ss - 2 K_si (row s of K,
+// read along the row), clamped at 0.  O(n) per seed, O(nk) for the labels.
+
+__device__ __forceinline__ float kentry(const float *K, int64_t idx) { return K[idx]; }
+__device__ __forceinline__ float kentry(const uint16_t *K, int64_t idx) {
+    return __uint_as_float((uint32_t)K[idx] << 16);
+}
+
+// dmin_i = min over seeds 0..t of the distance; block sums of kKppRows
+// consecutive rows in the same pairwise order as kpp_update.
+template <typename T>
+__global__ __launch_bounds__(256) void kkpp_update(const T *K, int64_t ldk, const float *diag,
+                                                   int64_t n, const int32_t *seeds, int t,
+                                                   float *dmin, double *bsum) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t sd = seeds[t];
+    float m = 0.f;
+    if (i < n) {
+        const float d = fmaxf(diag[i] + diag[sd] - 2.0f * kentry(K, sd * ldk + i), 0.0f);
+        m = (t == 0) ? d : fminf(dmin[i], d);
+        dmin[i] = m;
+    }
+    const double v = (double)m;
+    const int lane = threadIdx.x & 63;
+    const int g = lane & ~(kKppRows - 1);
+    const double v0 = __shfl(v, g, kWave), v1 = __shfl(v, g + 1, kWave);
+    const double v2 = __shfl(v, g + 2, kWave), v3 = __shfl(v, g + 3, kWave);
+    if ((lane & (kKppRows - 1)) == 0 && i < n) bsum[i / kKppRows] = (v0 + v1) + (v2 + v3);
+}
+
+// label_i = index of the nearest seed (lowest on ties)
+template <typename T>
+__global__ __launch_bounds__(256) void kkpp_assign(const T *K, int64_t ldk, const float *diag,
+                                                   int64_t n, int32_t k, const int32_t *seeds,
+                                                   int32_t *labels) {
+    extern __shared__ int32_t ss[];
+    for (int t = threadIdx.x; t < k; t += 256) ss[t] = seeds[t];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float di = diag[i];
+    float best = __builtin_inff();
+    int32_t arg = 0;
+    for (int32_t t = 0; t < k; ++t) {
+        const int64_t sd = ss[t];
+        const float d = fmaxf(di + diag[sd] - 2.0f * kentry(K, sd * ldk + i), 0.0f);
+        if (d < best) {
+            best = d;
+            arg = t;
+        }
+    }
+    labels[i] = arg;
+}
+
 __global__ void gather_seed_rows(const float *F, int64_t ldf, int64_t f, const int32_t *seeds,
                                  float *C) {
     const int64_t c = blockIdx.x;
@@ -397,6 +454,75 @@ extern "C" kkm_status kkm_feature_kmeanspp(const float *F, int64_t n, int64_t f,
     KKM_TRY(gemm_launch(GEMM_F32, true, true, EPI_STORE, g, s));
     hipLaunchKernelGGL(feature_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, fn,
                        cn, offs, n, k, lab_in, labels_out, changed, nullptr);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+extern "C" size_t kkm_kernel_kmeanspp_workspace_bytes(int64_t n, int32_t k) {
+    if (n < 1 || k < 1) return 0;
+    Carver c(nullptr);
+    c.take<float>((size_t)n);                                 // dmin
+    c.take<double>((size_t)((n + kKppRows - 1) / kKppRows));  // block sums
+    return c.bytes();
+}
+
+extern "C" kkm_status kkm_kernel_kmeanspp(const void *K, int32_t k_store, int64_t ldk,
+                                          const float *diagK, int64_t n, int32_t k,
+                                          const double *uniforms, int32_t *seeds,
+                                          int32_t *labels_out, void *ws, size_t ws_bytes,
+                                          void *stream) {
+    if (n < 1 || k < 1 || k > n || ldk < n || !K || !diagK || !uniforms || !seeds ||
+        !labels_out) {
+        set_error("kkm_kernel_kmeanspp: bad sizes or NULL pointer");
+        return KKM_ERR_ARG;
+    }
+    if (k_store != KKM_F32 && k_store != KKM_BF16) {
+        set_error("kkm_kernel_kmeanspp: K must be stored as KKM_F32 or KKM_BF16");
+        return KKM_ERR_ARG;
+    }
+    if (k > KKM_MAX_K) {
+        set_error("kkm_kernel_kmeanspp: k=%d exceeds KKM_MAX_K=%d", k, KKM_MAX_K);
+        return KKM_ERR_UNSUPPORTED;
+    }
+    for (int32_t t = 0; t < k; ++t)
+        if (!(uniforms[t] >= 0.0 && uniforms[t] < 1.0)) {
+            set_error("kkm_kernel_kmeanspp: uniforms must lie in [0, 1)");
+            return KKM_ERR_ARG;
+        }
+    const size_t need = kkm_kernel_kmeanspp_workspace_bytes(n, k);
+    if (!ws || ws_bytes < need) {
+        set_error("kkm_kernel_kmeanspp: workspace of %zu bytes is smaller than %zu", ws_bytes,
+                  need);
+        return KKM_ERR_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws);
+    float *dmin = c.take<float>((size_t)n);
+    const int64_t nb = (n + kKppRows - 1) / kKppRows;
+    double *bsum = c.take<double>((size_t)nb);
+    const int64_t first = (int64_t)(uniforms[0] * (double)n);
+    hipLaunchKernelGGL(fill_one_i32, dim3(1), dim3(1), 0, s, seeds,
+                       (int32_t)(first < n ? first : n - 1));
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    for (int32_t t = 0; t + 1 < k; ++t) {
+        if (k_store == KKM_F32)
+            hipLaunchKernelGGL(kkpp_update<float>, g, b, 0, s, static_cast<const float *>(K), ldk,
+                               diagK, n, seeds, t, dmin, bsum);
+        else
+            hipLaunchKernelGGL(kkpp_update<uint16_t>, g, b, 0, s,
+                               static_cast<const uint16_t *>(K), ldk, diagK, n, seeds, t, dmin,
+                               bsum);
+        hipLaunchKernelGGL(kpp_select, dim3(1), dim3(1024), 0, s, bsum, nb, dmin, n,
+                           uniforms[t + 1], seeds, t);
+        KKM_HIP(hipGetLastError());
+    }
+    const size_t lds = sizeof(int32_t) * (size_t)k;
+    if (k_store == KKM_F32)
+        hipLaunchKernelGGL(kkpp_assign<float>, g, b, lds, s, static_cast<const float *>(K), ldk,
+                           diagK, n, k, seeds, labels_out);
+    else
+        hipLaunchKernelGGL(kkpp_assign<uint16_t>, g, b, lds, s, static_cast<const uint16_t *>(K),
+                           ldk, diagK, n, k, seeds, labels_out);
     KKM_HIP(hipGetLastError());
     return KKM_OK;
 }
