@@ -89,3 +89,25 @@ def gram_bound(X, kernel, gamma, coef0, degree, K_or, dot_rel=0.0):
         sq_err = (d + 4) * u * (nr[:, None] + nr[None, :] + 2 * dot_abs) + 2 * dot_rel * dot_abs
         b = np.abs(K_or) * (gamma * sq_err + 4 * u)
     return 4.0 * b + 1e-30
+
+
+def gram_bound_pairs(X, I, J, kernel, gamma, coef0, degree, K_or, dot_rel=0.0):
+    """gram_bound for selected entries (I[t], J[t]) only, K_or the exact values
+    there: the same per-entry rule without forming the n x n matrices."""
+    u = 2.0 ** -24
+    Xd = np.abs(X.astype(np.float64))
+    d = X.shape[1]
+    dot_abs = (Xd[I] * Xd[J]).sum(axis=1)
+    dot_err = ((d + 2) * u + dot_rel) * dot_abs
+    if kernel == 0:
+        b = dot_err
+    elif kernel == 1:
+        Xs = X.astype(np.float64)
+        t = gamma * (Xs[I] * Xs[J]).sum(axis=1) + coef0
+        t_err = gamma * dot_err + u * (np.abs(t) + np.abs(coef0))
+        b = degree * np.abs(t) ** max(degree - 1, 0) * t_err + (degree + 1) * u * np.abs(K_or)
+    else:
+        nr = (Xd * Xd).sum(axis=1)
+        sq_err = (d + 4) * u * (nr[I] + nr[J] + 2 * dot_abs) + 2 * dot_rel * dot_abs
+        b = np.abs(K_or) * (gamma * sq_err + 4 * u)
+    return 4.0 * b + 1e-30
