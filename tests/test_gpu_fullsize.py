@@ -10,6 +10,8 @@ oracle can compute one by one:
   cluster means of E, each label is the argmin of its row of D, the sizes and
   the changed count follow from the labels, J is the sum of the own-cluster
   distances;
+* the precision form (BF16 product and K) and the feature map's forward pass
+  at n = 200000 on sampled rows;
 * batched: sampled problems of the 512-problem workload against their own
   single runs (bit for bit), and the tuned chunking against the default one.
 """
@@ -104,6 +106,83 @@ def test_gmm200k_full_size(kkm):
 
 def test_mnist_like_full_size(kkm):
     workload_step_check(kkm, datagen.WORKLOADS["mnist_like"])
+
+
+def test_gmm200k_bf16_full_size(kkm):
+    """The precision form at full size (BF16 product, K stored as bfloat16): the
+    oracle is fed the bfloat16-rounded points the product multiplies; K may
+    differ from it by the FP32 accumulation bound plus bfloat16's unit
+    roundoff of the stored value, and E by the mean of those."""
+    import torch
+    from quantref import bf16_round
+    w = datagen.WORKLOADS["gmm200k"]
+    dev = torch.device("cuda:0")
+    say("full size bf16:", w.name)
+    X, _ = w.points()
+    Xq = bf16_round(X).astype(np.float32)
+    l0 = w.labels0()
+    K, diag = kkm.kkm_gram(torch.from_numpy(X).to(dev), w.kernel, w.gamma, gram_prec=kkm.BF16,
+                           k_store=kkm.BF16)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(909)
+    n = w.n
+    I = np.concatenate([rng.integers(0, n, 2000), np.arange(n - 30, n)])
+    J = np.concatenate([rng.integers(0, n, 2000), rng.integers(0, n, 30)])
+    It, Jt = torch.from_numpy(I).to(dev), torch.from_numpy(J).to(dev)
+    kij = K[It, Jt].float().double().cpu().numpy()
+    assert np.array_equal(kij, K[Jt, It].float().double().cpu().numpy())
+    k_or = np.array([oracle.kappa(Xq[i], Xq[j], w.kernel, w.gamma) for i, j in zip(I, J)])
+    bound = gram_bound_pairs(Xq, I, J, w.kernel, w.gamma, 0.0, 1, k_or) + 2.0 ** -8 * np.abs(k_or)
+    assert (np.abs(kij - k_or) / bound).max() <= 1.0
+    say("  one step")
+    lab, cnt, ch, J_in, D, C = kkm.kkm_iterate(K, diag, torch.from_numpy(l0).to(dev), w.k,
+                                               D_out=True, ctilde_out=True)
+    torch.cuda.synchronize()
+    del K
+    torch.cuda.empty_cache()
+    D = D.cpu().numpy().astype(np.float64)
+    C = C.cpu().numpy().astype(np.float64)
+    dgl = diag.cpu().numpy().astype(np.float64)
+    lab = lab.cpu().numpy()
+    assert np.array_equal(lab, np.argmin(D, axis=1).astype(np.int32))
+    counts = np.bincount(l0, minlength=w.k).astype(np.float64)
+    E = 0.5 * (dgl[:, None] + C[None, :] - D)
+    R = np.unique(np.concatenate([rng.integers(0, n, 40), np.arange(n - 8, n)]))
+    S_or = oracle.cluster_row_sums(Xq, l0, w.k, R, w.kernel, w.gamma)
+    E_or = S_or / counts[None, :]
+    # per row: the mean over each cluster of the per-entry bounds, bounded by
+    # their maximum (rows' kernel values are <= 1 under the Gaussian)
+    sig = np.abs(dgl[R]) + (2 * np.abs(E_or) + np.abs(C)[None, :]).max(axis=1)
+    tol = 2.0 ** -8 * np.abs(E_or) + D_TOL * sig[:, None]
+    assert (np.abs(E[R] - E_or) <= tol).all(), (np.abs(E[R] - E_or) / tol).max()
+
+
+def test_feature_map_forward_full_size(kkm):
+    """phi_theta on all 200000 points of the mixture (the warm start's forward
+    pass), sampled rows against the FP64 reference with the same bfloat16
+    operand rounding."""
+    import torch
+    from oracle import mlp as omlp
+    w = datagen.WORKLOADS["gmm200k"]
+    X, _ = w.points()
+    th = datagen.mlp_init_params(w.d, 512, 512, 256, seed=910)
+    say("full size forward: n=%d d=%d" % X.shape)
+    F = kkm.kkm_mlp_forward(torch.from_numpy(th).cuda(), torch.from_numpy(X).cuda())
+    torch.cuda.synchronize()
+    R = np.unique(np.concatenate([np.random.default_rng(911).integers(0, w.n, 64),
+                                  np.arange(w.n - 8, w.n)]))
+    Fs = F[torch.from_numpy(R).cuda()].cpu().numpy().astype(np.float64)
+    ref, _ = omlp.forward(th.astype(np.float64), X[R], w.d, 512, 512, 256, bf16_operands=True)
+    # Both sides multiply bfloat16-rounded operands, accumulating in FP32 (GPU)
+    # or FP64 (reference).  An activation that lies next to a bfloat16 rounding
+    # midpoint can round to the other neighbour on one side, so the outputs may
+    # differ by a few operand spacings; the bar is one bfloat16 spacing (2^-7)
+    # of the output scale.  A wrong layer, bias or activation misses it by
+    # orders of magnitude.
+    err = np.abs(Fs - ref).max()
+    say("  forward error: %.3g (%.3g of one bfloat16 spacing of max|F|)" % (
+        err, err / (2.0 ** -7 * np.abs(ref).max())))
+    assert err <= 2.0 ** -7 * np.abs(ref).max(), err
 
 
 def test_batched_512_full_size(kkm):
