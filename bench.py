@@ -264,6 +264,37 @@ def batched_leg(kkm, torch, dev, iters):
     return out
 
 
+def gram_shapes(kkm, torch, dev):
+    """Triangle (SYRK work, mirrored stores) against full (GEMM work) tile shapes
+    of the FP32 Gram over n and d, the paper's architecture-dependent switch
+    (it switches to GEMM above n/d = 100 on its GPU).  Returns a list of rows."""
+    rows = []
+    for n in (20000, 60000, 100000):
+        K = kkm.alloc_kernel_matrix(n, kkm.F32, dev)
+        diag = torch.empty(n, dtype=torch.float32, device=dev)
+        for d in (16, 64, 256, 1024):
+            g = torch.Generator(device=dev)
+            g.manual_seed(n + d)
+            X = torch.randn(n, d, generator=g, device=dev)
+            row = {"n": n, "d": d, "n_over_d": n / d}
+            for name, shape in (("triangle_ms", kkm.GRAM_TRIANGLE), ("full_ms", kkm.GRAM_FULL)):
+                best = float("inf")
+                for _ in range(3):
+                    kkm.kkm_timing_enable(True)
+                    kkm.kkm_gram(X, kkm.GAUSS, 1.0 / d, K=K, diagK=diag, shape=shape)
+                    torch.cuda.synchronize()
+                    best = min(best, kkm.kkm_timing_read()["gram"][0])
+                    kkm.kkm_timing_enable(False)
+                row[name] = best
+            row["full_over_triangle"] = row["full_ms"] / row["triangle_ms"]
+            rows.append(row)
+            log("gram shapes n=%d d=%d: triangle %.2f ms, full %.2f ms" % (
+                n, d, row["triangle_ms"], row["full_ms"]))
+        del K
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +310,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched form and print its record")
+    ap.add_argument("--gram-shapes", action="store_true",
+                    help="time the triangle and full tile shapes of the Gram over n and d")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -294,6 +327,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.gram_shapes:
+        print(json.dumps({"gram_shapes": gram_shapes(kkm, torch, torch.device("cuda:0"))}),
+              flush=True)
         return
     if args.batched_only:
         print(json.dumps(batched_leg(kkm, torch, torch.device("cuda:0"), args.iters or 30)),

@@ -97,6 +97,21 @@ kkm_status kkm_gram(const float *X, int64_t n, int64_t d, int64_t ldx,
 
 size_t kkm_gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec);
 
+/* Tile shapes of the product (Sec. 4.2 weighs GEMM against SYRK and switches at
+ * a tuned n/d threshold): KKM_GRAM_TRIANGLE multiplies the tiles on and above
+ * the diagonal only and stores each value at (i, j) and (j, i) (the SYRK
+ * work); KKM_GRAM_FULL multiplies every tile of the square, each storing its
+ * own block (the GEMM work, twice the flops, one store per value).  Both give
+ * the same, exactly symmetric K. */
+typedef enum { KKM_GRAM_TRIANGLE = 0, KKM_GRAM_FULL = 1 } kkm_gram_shape;
+
+/* kkm_gram_ex — kkm_gram with the tile shape chosen (kkm_gram uses
+ * KKM_GRAM_TRIANGLE).  KKM_ERR_ARG for an unknown shape. */
+kkm_status kkm_gram_ex(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t kernel_type,
+                       double gamma, double coef0, int32_t degree, int32_t gram_prec,
+                       int32_t k_store, int32_t shape, void *K, int64_t ldk, float *diagK,
+                       void *ws, size_t ws_bytes, void *stream);
+
 /*
  * kkm_iterate — one reassignment step (Algorithm 2 loop body) for labels_in:
  * builds V in CSR form from the labels (Sec. 4.1), E = K V^T by a row sweep of

@@ -11,7 +11,8 @@ from ._binding import (BF16, EMPTY_INF, EMPTY_ZERO_CENTROID, EXPORTS, F32, FP8_R
                        kkm_timing_enable, kkm_timing_read, lib, mlp_param_count, kkm_mlp_forward,
                        kkm_mlp_loss_grad, kkm_mlp_adam, kkm_mlp_train, kkm_feature_lloyd,
                        kkm_feature_kmeanspp, kkm_mlp_train_fresh, kkm_fit_batched,
-                       kkm_fit_batched_workspace_bytes, KkmInstance, kkm_kernel_kmeanspp, kkm_refine)
+                       kkm_fit_batched_workspace_bytes, KkmInstance, kkm_kernel_kmeanspp, kkm_refine,
+                       GRAM_TRIANGLE, GRAM_FULL)
 
 __all__ = ["kkm_gram", "kkm_iterate", "kkm_fit", "kkm_fit_ex", "kkm_timing_enable",
            "kkm_timing_read", "mlp_param_count", "kkm_mlp_forward", "kkm_mlp_loss_grad",
@@ -19,4 +20,5 @@ __all__ = ["kkm_gram", "kkm_iterate", "kkm_fit", "kkm_fit_ex", "kkm_timing_enabl
            "gram_workspace_bytes", "iterate_workspace_bytes", "KKMError", "lib", "EXPORTS",
            "LINEAR", "POLY", "GAUSS", "F32", "BF16", "FP8_ROWSCALED", "EMPTY_INF",
            "EMPTY_ZERO_CENTROID", "MAX_K", "kkm_fit_batched", "kkm_fit_batched_workspace_bytes",
-           "KkmInstance", "kkm_feature_kmeanspp", "kkm_mlp_train_fresh", "kkm_kernel_kmeanspp", "kkm_refine"]
+           "KkmInstance", "kkm_feature_kmeanspp", "kkm_mlp_train_fresh", "kkm_kernel_kmeanspp", "kkm_refine",
+           "GRAM_TRIANGLE", "GRAM_FULL"]

@@ -22,7 +22,7 @@ _STATUS = {0: "KKM_OK", -1: "KKM_ERR_ARG", -2: "KKM_ERR_LABEL", -3: "KKM_ERR_NOM
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkkm.so")
 
-EXPORTS = ("kkm_gram", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_workspace_bytes",
+EXPORTS = ("kkm_gram", "kkm_gram_ex", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_workspace_bytes",
            "kkm_fit", "kkm_fit_ex", "kkm_mlp_param_count", "kkm_mlp_forward",
            "kkm_mlp_forward_workspace_bytes", "kkm_mlp_loss_grad", "kkm_mlp_train_workspace_bytes",
            "kkm_mlp_adam", "kkm_mlp_train", "kkm_feature_lloyd", "kkm_feature_lloyd_workspace_bytes",
@@ -63,6 +63,9 @@ def lib():
         L.kkm_gram_workspace_bytes.argtypes = [_i64, _i64, _i32]
         L.kkm_iterate_workspace_bytes.restype = _sz
         L.kkm_iterate_workspace_bytes.argtypes = [_i64, _i32]
+        L.kkm_gram_ex.restype = ctypes.c_int
+        L.kkm_gram_ex.argtypes = [_vp, _i64, _i64, _i64, _i32, _d, _d, _i32, _i32, _i32, _i32,
+                                  _vp, _i64, _vp, _vp, _sz, _vp]
         L.kkm_gram.restype = ctypes.c_int
         L.kkm_gram.argtypes = [_vp, _i64, _i64, _i64, _i32, _d, _d, _i32, _i32, _i32, _vp, _i64,
                                _vp, _vp, _sz, _vp]
@@ -180,9 +183,13 @@ def iterate_workspace_bytes(n: int, k: int) -> int:
     return int(lib().kkm_iterate_workspace_bytes(n, k))
 
 
+GRAM_TRIANGLE, GRAM_FULL = 0, 1
+
+
 def kkm_gram(X, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram_prec=F32, k_store=F32,
-             K=None, diagK=None, ws=None):
-    """K = kappa(X X^T) and diag(K) on the GPU.  Returns (K, diagK)."""
+             K=None, diagK=None, ws=None, shape=GRAM_TRIANGLE):
+    """K = kappa(X X^T) and diag(K) on the GPU.  Returns (K, diagK).  shape:
+    GRAM_TRIANGLE (upper-triangle tiles, mirrored stores) or GRAM_FULL (every tile)."""
     _dev(X, torch.float32, "X", 2)
     n, d, ldx = _rows(X, "X")
     if K is None:
@@ -197,8 +204,9 @@ def kkm_gram(X, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram_prec=F32, k_s
     need = gram_workspace_bytes(n, d, gram_prec)
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
-    _check(lib().kkm_gram(_ptr(X), n, d, ldx, kernel, gamma, coef0, degree, gram_prec, k_store,
-                          _ptr(K), ldk, _ptr(diagK), _ptr(ws), ws.numel(), _stream()))
+    _check(lib().kkm_gram_ex(_ptr(X), n, d, ldx, kernel, gamma, coef0, degree, gram_prec,
+                             k_store, shape, _ptr(K), ldk, _ptr(diagK), _ptr(ws), ws.numel(),
+                             _stream()))
     return K, diagK
 
 

@@ -26,11 +26,6 @@ kkm_status hip_fail(hipError_t e, const char *what) {
     return (e == hipErrorOutOfMemory) ? KKM_ERR_NOMEM : KKM_ERR_HIP;
 }
 
-size_t gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec);
-kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t kernel,
-                       double gamma, double coef0, int32_t degree, int32_t gram_prec,
-                       int32_t k_store, void *K, int64_t ldk, float *diagK, void *ws,
-                       size_t ws_bytes, hipStream_t stream);
 size_t iterate_workspace_bytes(int64_t n, int32_t k);
 kkm_status iterate_launch(const void *K, int32_t k_store, int64_t ldk, const float *diagK,
                           int64_t n, int32_t k, const int32_t *labels_in, int32_t empty_policy,
@@ -200,20 +195,33 @@ extern "C" size_t kkm_iterate_workspace_bytes(int64_t n, int32_t k) {
     return iterate_workspace_bytes(n, k);
 }
 
-extern "C" kkm_status kkm_gram(const float *X, int64_t n, int64_t d, int64_t ldx,
-                               int32_t kernel_type, double gamma, double coef0, int32_t degree,
-                               int32_t gram_prec, int32_t k_store, void *K, int64_t ldk,
-                               float *diagK, void *ws, size_t ws_bytes, void *stream) {
+extern "C" kkm_status kkm_gram_ex(const float *X, int64_t n, int64_t d, int64_t ldx,
+                                  int32_t kernel_type, double gamma, double coef0,
+                                  int32_t degree, int32_t gram_prec, int32_t k_store,
+                                  int32_t shape, void *K, int64_t ldk, float *diagK, void *ws,
+                                  size_t ws_bytes, void *stream) {
     g_err[0] = 0;
     if (n < 1 || d < 1 || ldx < d || ldk < n || !X || !K || !diagK) {
         set_error("kkm_gram: bad sizes or NULL pointer (n=%lld d=%lld ldx=%lld ldk=%lld)",
                   (long long)n, (long long)d, (long long)ldx, (long long)ldk);
         return KKM_ERR_ARG;
     }
+    if (shape != KKM_GRAM_TRIANGLE && shape != KKM_GRAM_FULL) {
+        set_error("kkm_gram: unknown shape %d", shape);
+        return KKM_ERR_ARG;
+    }
     KKM_TRY(check_kernel(kernel_type, gamma, coef0, degree));
     KKM_TRY(check_dtypes(gram_prec, k_store));
     return gram_launch(X, n, d, ldx, kernel_type, gamma, coef0, degree, gram_prec, k_store, K,
-                       ldk, diagK, ws, ws_bytes, (hipStream_t)stream);
+                       ldk, diagK, ws, ws_bytes, (hipStream_t)stream, shape);
+}
+
+extern "C" kkm_status kkm_gram(const float *X, int64_t n, int64_t d, int64_t ldx,
+                               int32_t kernel_type, double gamma, double coef0, int32_t degree,
+                               int32_t gram_prec, int32_t k_store, void *K, int64_t ldk,
+                               float *diagK, void *ws, size_t ws_bytes, void *stream) {
+    return kkm_gram_ex(X, n, d, ldx, kernel_type, gamma, coef0, degree, gram_prec, k_store,
+                       KKM_GRAM_TRIANGLE, K, ldk, diagK, ws, ws_bytes, stream);
 }
 
 extern "C" kkm_status kkm_iterate(const void *K, int32_t k_store, int64_t ldk,

@@ -31,22 +31,22 @@ using namespace gt;
 
 // ---------------------------------------------------------------- FP32 product
 
-template <typename OUT>
+template <typename OUT, bool FULL>
 __global__ __launch_bounds__(GTHREADS, 2) void gram_f32_mfma(F32Tile a, TileOrder o) {
     __shared__ __attribute__((aligned(16))) F32Lds lds;
     int64_t bi, bj;
     if (!tile_of_block(o, bi, bj)) return;
-    f32_tile<OUT>(a, bi, bj, lds);
+    f32_tile<OUT, FULL>(a, bi, bj, lds);
 }
 
 // ---------------------------------------------------------------- BF16 / FP8 product
 
-template <int PREC, typename OUT>
+template <int PREC, typename OUT, bool FULL>
 __global__ __launch_bounds__(GTHREADS, 2) void gram_lowp_mfma(LowpTile a, TileOrder o) {
     __shared__ __attribute__((aligned(16))) LowpLds lds;
     int64_t bi, bj;
     if (!tile_of_block(o, bi, bj)) return;
-    lowp_tile<PREC, OUT>(a, bi, bj, lds);
+    lowp_tile<PREC, OUT, FULL>(a, bi, bj, lds);
 }
 
 // ---------------------------------------------------------------- prologues
@@ -73,6 +73,21 @@ __global__ __launch_bounds__(256) void quantize_rows(const float *X, int64_t n, 
                        threadIdx.x & 63);
 }
 
+template <bool FULL>
+void lowp_dispatch(int32_t gram_prec, int32_t k_store, dim3 g, dim3 b, const LowpTile &a,
+                   const TileOrder &order, hipStream_t stream) {
+    if (gram_prec == KKM_BF16 && k_store == KKM_F32)
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, float, FULL>), g, b, 0, stream, a, order);
+    else if (gram_prec == KKM_BF16)
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, uint16_t, FULL>), g, b, 0, stream, a, order);
+    else if (k_store == KKM_F32)
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, float, FULL>), g, b, 0, stream, a,
+                           order);
+    else
+        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, uint16_t, FULL>), g, b, 0, stream,
+                           a, order);
+}
+
 // log2 of the tile group edge of the launch order: 8 x 8 groups, so the 64
 // tiles an XCD holds at once (32 CUs x 2 workgroups) read 16 operand panels.
 int group_log2(int64_t d, int32_t gram_prec) {
@@ -97,7 +112,7 @@ size_t gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec) {
 kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t kernel,
                        double gamma, double coef0, int32_t degree, int32_t gram_prec,
                        int32_t k_store, void *K, int64_t ldk, float *diagK, void *ws,
-                       size_t ws_bytes, hipStream_t stream) {
+                       size_t ws_bytes, hipStream_t stream, int32_t shape) {
     const size_t need = gram_workspace_bytes(n, d, gram_prec);
     if (ws == nullptr || ws_bytes < need) {
         set_error("kkm_gram: workspace of %zu bytes is smaller than %zu", ws_bytes, need);
@@ -119,7 +134,8 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
     const uintptr_t kaddr = reinterpret_cast<uintptr_t>(K);
     e.vec_k = (k_store == KKM_F32) ? (((ldk % 4) == 0) && ((kaddr & 15) == 0))
                                    : (((ldk % 4) == 0) && ((kaddr & 7) == 0));
-    const TileOrder order = tile_order(n, group_log2(d, gram_prec));
+    const bool full = (shape == KKM_GRAM_FULL);
+    const TileOrder order = tile_order(n, group_log2(d, gram_prec), full);
     const int64_t grid = order.per_xcd * 8;
     if (grid > 0x7fffffff) {
         set_error("kkm_gram: n=%lld needs more than 2^31 tiles", (long long)n);
@@ -139,12 +155,15 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
         a.vec_x = ((ldx % 4) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
         a.e = e;
         const TimedSpan span = timing_begin(TK_GRAM, stream);
-        if (k_store == KKM_F32)
-            hipLaunchKernelGGL(gram_f32_mfma<float>, dim3((unsigned)grid), dim3(GTHREADS), 0,
-                               stream, a, order);
+        const dim3 g((unsigned)grid), b(GTHREADS);
+        if (k_store == KKM_F32 && !full)
+            hipLaunchKernelGGL((gram_f32_mfma<float, false>), g, b, 0, stream, a, order);
+        else if (k_store == KKM_F32)
+            hipLaunchKernelGGL((gram_f32_mfma<float, true>), g, b, 0, stream, a, order);
+        else if (!full)
+            hipLaunchKernelGGL((gram_f32_mfma<uint16_t, false>), g, b, 0, stream, a, order);
         else
-            hipLaunchKernelGGL(gram_f32_mfma<uint16_t>, dim3((unsigned)grid), dim3(GTHREADS), 0,
-                               stream, a, order);
+            hipLaunchKernelGGL((gram_f32_mfma<uint16_t, true>), g, b, 0, stream, a, order);
         KKM_HIP(hipGetLastError());
         timing_end(span, stream);
         return KKM_OK;
@@ -169,14 +188,10 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
     if (gram_prec == KKM_FP8_ROWSCALED) a.e.scale = scale;
     const TimedSpan span = timing_begin(TK_GRAM, stream);
     const dim3 g((unsigned)grid), b(GTHREADS);
-    if (gram_prec == KKM_BF16 && k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, float>), g, b, 0, stream, a, order);
-    else if (gram_prec == KKM_BF16)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, uint16_t>), g, b, 0, stream, a, order);
-    else if (k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, float>), g, b, 0, stream, a, order);
+    if (!full)
+        lowp_dispatch<false>(gram_prec, k_store, g, b, a, order, stream);
     else
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, uint16_t>), g, b, 0, stream, a, order);
+        lowp_dispatch<true>(gram_prec, k_store, g, b, a, order, stream);
     KKM_HIP(hipGetLastError());
     timing_end(span, stream);
     return KKM_OK;

@@ -104,13 +104,63 @@ __device__ __forceinline__ void stage_norms(const Epi &e, int64_t m0, int64_t n0
 // (EPI_LDS_BYTES) may alias the operand buffers: the caller's last barrier
 // has retired every read of them.  The trailing barrier retires every read of
 // `T`, `rn` and `rs` before the workgroup's next tile.
-template <typename OUT>
+//
+// FULL (every tile of the square is launched, the GEMM shape of the product):
+// each tile writes only its own block K[i][j], through `T` as is; a diagonal
+// tile also writes diag(K).  Tile (j, i) multiplies the same products in the
+// same order as tile (i, j), so K is still exactly symmetric.
+template <typename OUT, bool FULL>
 __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int64_t m0,
                                          int64_t n0, bool diag_tile, int wr, int wc, int lane,
                                          float *T, const float *rn, const float *rs) {
     const int half = lane >> 5, l32 = lane & 31;
     const int tid = threadIdx.x;
     const int c4 = (tid & 31) * 4;
+    if constexpr (FULL) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) {
+                const int jj = wc * 64 + ni * 32 + l32;
+                const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
+#pragma unroll
+                for (int rg = 0; rg < 4; ++rg) {
+                    const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float b = acc[mi][ni][4 * rg + r];
+                        if (e.scale) b *= rs[ii0 + r] * s_j;
+                        float v = kappa_from_dot(b, rn[ii0 + r], nrm_j, e.kernel, e.gamma,
+                                                 e.coef0, e.degree);
+                        if (diag_tile && ii0 + r == jj) {
+                            // kappa(x, x) = exp(0) = 1 exactly; a non-finite row stays visible
+                            v = (e.kernel == KKM_GAUSS) ? (isfinite(b) ? 1.0f : __builtin_nanf(""))
+                                                        : Store<OUT>::round(v);
+                            if (m0 + jj < e.n) e.diag[m0 + jj] = v;
+                        }
+                        T[(ii0 + r) * TS + jj] = v;
+                    }
+                }
+            }
+        __syncthreads();
+        // K[m0 + ii][n0 .. n0 + 127]; rows and columns may pass n
+        for (int ii = tid >> 5; ii < GM; ii += GTHREADS / 32) {
+            const int64_t gi = m0 + ii, gj0 = n0 + c4;
+            if (gi >= e.n || gj0 >= e.n) continue;
+            const f32x4 w = *reinterpret_cast<const f32x4 *>(T + ii * TS + c4);
+            const float v[4] = {w[0], w[1], w[2], w[3]};
+            const int64_t idx = gi * e.ldk + gj0;
+            if (e.vec_k && gj0 + 3 < e.n) {
+                Store<OUT>::four(e.K, idx, v);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (gj0 + r < e.n) Store<OUT>::one(e.K, idx + r, v[r]);
+            }
+        }
+        __syncthreads();
+        return;
+    }
     if (!diag_tile) {
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
@@ -236,17 +286,20 @@ __device__ __forceinline__ void tile_coords(int64_t t, int64_t &bi, int64_t &bj)
 // 2g operand panels in its L2 instead of one panel per tile.
 struct TileOrder {
     int64_t nb;        // tiles per side
-    int64_t npos;      // positions: G (G + 1) / 2 * g^2, G = ceil(nb / g)
+    int64_t G;         // groups per side, ceil(nb / g)
+    int64_t npos;      // positions: G (G + 1) / 2 * g^2 (triangle) or G^2 g^2 (full)
     int64_t per_xcd;   // positions per XCD
     int lg;            // log2 g
+    int full;          // every tile of the square (else the upper triangle)
 };
 
-inline TileOrder tile_order(int64_t n, int lg) {
+inline TileOrder tile_order(int64_t n, int lg, bool full = false) {
     TileOrder o;
     o.nb = (n + GM - 1) / GM;
     o.lg = lg;
-    const int64_t G = (o.nb + (int64_t(1) << lg) - 1) >> lg;
-    o.npos = (G * (G + 1) / 2) << (2 * lg);
+    o.full = full;
+    o.G = (o.nb + (int64_t(1) << lg) - 1) >> lg;
+    o.npos = (full ? o.G * o.G : o.G * (o.G + 1) / 2) << (2 * lg);
     o.per_xcd = (o.npos + 7) / 8;
     return o;
 }
@@ -256,6 +309,15 @@ __device__ __forceinline__ bool tile_of_block(const TileOrder &o, int64_t &bi, i
     const int64_t t = (pid % 8) * o.per_xcd + pid / 8;
     if (t >= o.npos) return false;
     int64_t I, J;
+    if (o.full) {
+        const int64_t sgrp = t >> (2 * o.lg);
+        I = sgrp % o.G;
+        J = sgrp / o.G;
+        const int64_t w = t & ((int64_t(1) << (2 * o.lg)) - 1);
+        bi = (I << o.lg) + (w & ((int64_t(1) << o.lg) - 1));
+        bj = (J << o.lg) + (w >> o.lg);
+        return bi < o.nb && bj < o.nb;
+    }
     tile_coords(t >> (2 * o.lg), I, J);
     const int64_t w = t & ((int64_t(1) << (2 * o.lg)) - 1);
     const int64_t g1 = (int64_t(1) << o.lg) - 1;
@@ -297,7 +359,7 @@ __device__ __forceinline__ f32x4 load_row4(const F32Tile &a, int64_t row, int64_
 }
 
 // One 128 x 128 tile (bi, bj) of the FP32 product and its epilogue.
-template <typename OUT>
+template <typename OUT, bool FULL = false>
 __device__ __forceinline__ void f32_tile(const F32Tile &a, int64_t bi, int64_t bj, F32Lds &lds) {
     const int64_t m0 = bi * GM, n0 = bj * GM;
 
@@ -372,7 +434,7 @@ __device__ __forceinline__ void f32_tile(const F32Tile &a, int64_t bi, int64_t b
         __syncthreads();
     }
     static_assert(sizeof(lds.op) >= EPI_LDS_BYTES, "epilogue tile does not fit");
-    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane, &lds.op[0][0][0], lds.rn, lds.rs);
+    epilogue<OUT, FULL>(a.e, acc, m0, n0, bi == bj, wr, wc, lane, &lds.op[0][0][0], lds.rn, lds.rs);
 }
 
 // Squared norm of one FP32 row (Gaussian, FP32 product), by one whole wave.
@@ -411,7 +473,7 @@ inline int64_t padded_d(int64_t d, int32_t gram_prec) {
 
 // One 128 x 128 tile (bi, bj) of the product and its epilogue, by the 256
 // threads of a workgroup, staging through `lds`.
-template <int PREC, typename OUT>
+template <int PREC, typename OUT, bool FULL = false>
 __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t bj, LowpLds &lds) {
     const int64_t m0 = bi * GM, n0 = bj * GM;
 
@@ -510,8 +572,8 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
         __syncthreads();
     }
     static_assert(sizeof(lds.op) >= EPI_LDS_BYTES, "epilogue tile does not fit");
-    epilogue<OUT>(a.e, acc, m0, n0, bi == bj, wr, wc, lane,
-                  reinterpret_cast<float *>(&lds.op[0][0][0]), lds.rn, lds.rs);
+    epilogue<OUT, FULL>(a.e, acc, m0, n0, bi == bj, wr, wc, lane,
+                        reinterpret_cast<float *>(&lds.op[0][0][0]), lds.rn, lds.rs);
 }
 
 __device__ __forceinline__ float wave_max(float v) {

@@ -58,10 +58,12 @@ void flag_nonfinite(const float *v, int64_t n, int32_t *flag, hipStream_t stream
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream);
 
 size_t gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec);
+// shape: KKM_GRAM_TRIANGLE (upper-triangle tiles, mirrored stores) or
+// KKM_GRAM_FULL (every tile, each storing its own block).
 kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t kernel,
                        double gamma, double coef0, int32_t degree, int32_t gram_prec,
                        int32_t k_store, void *K, int64_t ldk, float *diagK, void *ws,
-                       size_t ws_bytes, hipStream_t stream);
+                       size_t ws_bytes, hipStream_t stream, int32_t shape = KKM_GRAM_TRIANGLE);
 
 // ---------------------------------------------------------------- workspace carving
 

@@ -221,3 +221,19 @@ def test_error_paths(kkm):
     with pytest.raises(kkm.KKMError) as e:
         kkm.kkm_fit(Xd, 0, to_dev(np.zeros(300, np.int32)), kkm.GAUSS, 0.5)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("gp,ks", [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0), (2, 1)])
+@pytest.mark.parametrize("n,d", [(1, 3), (129, 33), (700, 100), (1100, 64)])
+def test_full_shape_equals_triangle(kkm, gp, ks, n, d):
+    """The GEMM shape (every tile) gives bit for bit the K and diag(K) of the
+    SYRK shape (upper triangle, mirrored), for every precision pair."""
+    import torch
+    X = np.random.default_rng(n + d).normal(0, 1, (n, d)).astype(np.float32)
+    Xd = to_dev(X)
+    for kern, g in ((kkm.GAUSS, 1.0 / d), (kkm.POLY, 0.1)):
+        a, da = kkm.kkm_gram(Xd, kern, g, 1.0, 2, gram_prec=gp, k_store=ks)
+        b, db = kkm.kkm_gram(Xd, kern, g, 1.0, 2, gram_prec=gp, k_store=ks, shape=kkm.GRAM_FULL)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), (gp, ks, kern)
+        assert torch.equal(da, db)
