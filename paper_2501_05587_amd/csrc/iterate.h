@@ -25,7 +25,6 @@ struct Inst {
     int32_t *perm, *offsets, *counts, *blk_hist, *blk_bad, *err;
     float *P, *Zp, *ctilde;
     double *Jpart;
-    uint32_t *ticket;
     // outputs of the step
     int32_t *counts_out;
     int64_t *n_changed;
@@ -83,7 +82,7 @@ int64_t inst_sweep_items(const InstGeom &g, int32_t k_store);
 // Sets the strip counts that depend on the element type of K.
 void inst_set_store(Inst *in, int32_t k_store);
 
-// The six kernels of one step over the whole set.  total_blocks,
+// The seven kernels of one step over the whole set.  total_blocks,
 // total_clusters and sweep_grid are grid sizes: label blocks, clusters and
 // sweep items summed over every problem the set can hold; max_k sizes the
 // dynamic LDS; vec: every K row is 16-byte aligned.
@@ -94,6 +93,6 @@ kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clu
 kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
                       int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,
                       int32_t *offsets, int32_t *counts_out, int64_t *n_changed,
-                      uint32_t *ticket, hipStream_t stream);
+                      hipStream_t stream);
 
 }  // namespace kkm

@@ -159,10 +159,7 @@ __global__ __launch_bounds__(kPtsPerBlock) void v_scatter(InstSet s, const int32
     if (lb == 0) {
         for (int c = tid; c <= k; c += kPtsPerBlock) in.offsets[c] = off[c];
         for (int c = tid; c < k; c += kPtsPerBlock) in.counts_out[c] = 0;
-        if (tid == 0) {
-            *in.n_changed = 0;
-            *in.ticket = 0u;
-        }
+        if (tid == 0) *in.n_changed = 0;
     }
 
     const int64_t i = lb * kPtsPerBlock + tid;
@@ -470,7 +467,6 @@ __global__ __launch_bounds__(kPtsPerBlock) void assign_fused(InstSet s,
     extern __shared__ int32_t sh[];  // off[k+1], hist[k], seg[kSlotWindow]
     __shared__ double wJ[kPtsPerBlock / kWave];
     __shared__ long long wC[kPtsPerBlock / kWave];
-    __shared__ bool last;
     Inst in;
     int64_t lb;
     if (!locate<MULTI>(s, s.blk_start, blockIdx.x, in, lb)) return;
@@ -593,14 +589,25 @@ __global__ __launch_bounds__(kPtsPerBlock) void assign_fused(InstSet s,
     }
     for (int c = tid; c < k; c += kPtsPerBlock)
         if (hist[c]) atomicAdd(&in.counts_out[c], hist[c]);
+}
 
-    // the problem's last block to finish sums its block partials of J in order
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = (atomicAdd(in.ticket, 1u) == (uint32_t)(in.nblk - 1));
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+// J of the input labels: each problem's block partials summed in a fixed
+// order by one workgroup (a kernel of its own: a device-wide release fence
+// in every assignment workgroup costs far more than this launch).
+template <bool MULTI>
+__global__ __launch_bounds__(kPtsPerBlock) void j_finalize(InstSet s) {
+    __shared__ double wJ[kPtsPerBlock / kWave];
+    Inst in;
+    if constexpr (MULTI) {
+        const int32_t b = blockIdx.x;
+        if (b >= s.count) return;
+        if (uniform_load(s.blk_start + b) >= uniform_load(s.blk_start + s.count)) return;
+        in = uniform_load(s.table + b);
+    } else {
+        in = s.one;
+    }
+    if (*in.err != 0) return;  // the assignment has published NaN
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double acc = 0.0;
     for (int64_t t = tid; t < in.nblk; t += kPtsPerBlock) acc += in.Jpart[t];
     const double ws = wave_sum(acc);
@@ -656,7 +663,6 @@ void inst_carve(void *base, const InstGeom &g, Inst *in, size_t *bytes) {
     float *Zp = c.take<float>((size_t)g.slots * (size_t)g.nws_max);
     float *ctilde = c.take<float>((size_t)g.k);
     double *Jpart = c.take<double>((size_t)g.nblk);
-    uint32_t *ticket = c.take<uint32_t>(1);
     if (bytes) *bytes = c.bytes();
     if (!in) return;
     in->n = g.n;
@@ -674,7 +680,6 @@ void inst_carve(void *base, const InstGeom &g, Inst *in, size_t *bytes) {
     in->Zp = Zp;
     in->ctilde = ctilde;
     in->Jpart = Jpart;
-    in->ticket = ticket;
 }
 
 int64_t inst_sweep_items(const InstGeom &g, int32_t k_store) {
@@ -728,6 +733,8 @@ kkm_status step_launch_t(const InstSet &s, int64_t total_blocks, int64_t total_c
                        (size_t)(2 * max_k + 1 + kSlotWindow) * sizeof(int32_t), stream, s,
                        labels_in, labels_out);
     KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(j_finalize<MULTI>, dim3(MULTI ? (unsigned)s.count : 1u), pb, 0, stream, s);
+    KKM_HIP(hipGetLastError());
     timing_end(whole, stream);
     return KKM_OK;
 }
@@ -749,7 +756,7 @@ kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clu
 kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
                       int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,
                       int32_t *offsets, int32_t *counts_out, int64_t *n_changed,
-                      uint32_t *ticket, hipStream_t stream) {
+                      hipStream_t stream) {
     InstSet s{};
     s.count = 1;
     Inst &in = s.one;
@@ -764,7 +771,6 @@ kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_
     in.offsets = offsets;
     in.counts_out = counts_out;
     in.n_changed = n_changed;
-    in.ticket = ticket;
     const dim3 pb(kPtsPerBlock);
     hipLaunchKernelGGL(v_block_hist<false>, dim3((unsigned)in.nblk), pb, (size_t)(k + 1) * sizeof(int32_t),
                        stream, s, labels);

@@ -16,7 +16,7 @@ namespace kkm {
 kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
                       int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,
                       int32_t *offsets, int32_t *counts_out, int64_t *n_changed,
-                      uint32_t *ticket, hipStream_t stream);
+                      hipStream_t stream);
 
 namespace {
 
@@ -25,7 +25,6 @@ constexpr int64_t kRows = 64;  // CSR positions per centroid-sum chunk
 struct LloydWs {
     int32_t *blk_hist, *blk_bad, *err, *counts, *perm, *offsets, *counts_out;
     int64_t *changed;
-    uint32_t *ticket;
     float *fn, *Cp, *C, *cn, *G;
     int32_t *lab[2];
     double *part, *obj;
@@ -44,7 +43,6 @@ LloydWs carve_lloyd(void *base, int64_t n, int64_t f, int32_t k, size_t *bytes) 
     w.offsets = c.take<int32_t>((size_t)k + 1);
     w.counts_out = c.take<int32_t>((size_t)k);
     w.changed = c.take<int64_t>(1);
-    w.ticket = c.take<uint32_t>(1);
     w.fn = c.take<float>((size_t)n);
     w.Cp = c.take<float>((size_t)(slots * f));
     w.C = c.take<float>((size_t)(k * f));
@@ -214,79 +212,212 @@ __global__ __launch_bounds__(256) void sum_blocks(const double *part, int64_t np
 // dmin_i is the squared distance of row i to its nearest seed so far.  The
 // uniforms u_t come from the caller.  Sums run in FP64 in a fixed order.
 
-constexpr int kKppRows = 4;  // rows per block (one wave each)
+// The running sum is kept in three levels of FP64 sums: blocks of kKppRows
+// rows, groups of kKppGroup rows (one update workgroup), and the total.  The
+// update kernel writes the first two; a one-workgroup select kernel then
+// locates the crossing level by level with block scans: ranges of groups,
+// then groups, then blocks, then rows.  Each level takes the first element
+// whose inclusive running sum passes the target, or its last element if
+// rounding leaves the target at its very end.
 
-__global__ __launch_bounds__(256) void kpp_update(const float *F, int64_t n, int64_t f,
-                                                  int64_t ldf, const int32_t *seeds, int t,
-                                                  float *dmin, double *bsum) {
-    __shared__ double rs[kKppRows];
-    const int64_t row = (int64_t)blockIdx.x * kKppRows + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    double dm = 0.0;
-    if (row < n) {
-        const float *c = F + (int64_t)seeds[t] * ldf;
-        const float *x = F + row * ldf;
-        float s = 0.f;
-        for (int64_t u = lane; u < f; u += kWave) {
-            const float e = x[u] - c[u];
-            s = fmaf(e, e, s);
-        }
-        s = wave_sum(s);
-        const float prev = (t == 0) ? __builtin_inff() : dmin[row];
-        const float m = fminf(prev, s);
-        if (lane == 0) dmin[row] = m;
-        dm = (double)m;
+constexpr int kKppRows = 4;
+constexpr int kKppGroup = 256;
+constexpr int kKppPerGroup = kKppGroup / kKppRows;  // block sums per group
+
+struct KppSums {
+    double *bsum;  // [ceil(n / kKppRows)]
+    double *gsum;  // [ceil(n / kKppGroup)]
+};
+
+// Scan of one value per thread over a 256-thread workgroup (fixed order):
+// returns the inclusive sum, with the exclusive sum in *excl and the total in
+// *total.  The exclusive sum of thread i is bit for bit the inclusive sum of
+// thread i-1, and the total that of thread 255, so "the first thread whose
+// running sum passes a target" is well defined and consistent with the total.
+__device__ double block_scan256(double v, double *sh, double *excl, double *total) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const double o = __shfl_up(v, off, kWave);
+        if (lane >= off) v += o;
     }
-    if (lane == 0) rs[threadIdx.x >> 6] = dm;
+    const double prev = __shfl_up(v, 1, kWave);
+    if (lane == kWave - 1) sh[w] = v;
     __syncthreads();
-    if (threadIdx.x == 0) bsum[blockIdx.x] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+    double base = 0.0;
+    for (int q = 0; q < w; ++q) base += sh[q];
+    double t = 0.0;
+    for (int q = 0; q < 4; ++q) t += sh[q];
+    *total = t;
+    *excl = (lane == 0) ? base : base + prev;
+    __syncthreads();
+    return base + v;
 }
 
-// One workgroup: picks seed t+1 from the block sums and dmin.  Thread r sums
-// its range of block sums; a block scan of the range sums locates the range
-// that holds u * total, and that range's thread walks its block sums and rows.
-__global__ __launch_bounds__(1024) void kpp_select(const double *bsum, int64_t nb, const float *dmin,
-                                                   int64_t n, double u, int32_t *seeds, int t) {
-    __shared__ double scan[2][1024];
-    const int tid = threadIdx.x;
-    const int64_t per = (nb + 1023) / 1024;
-    const int64_t b0 = min(nb, (int64_t)tid * per), b1 = min(nb, b0 + per);
-    double s = 0.0;
-    for (int64_t b = b0; b < b1; ++b) s += bsum[b];
-    int cur = 0;
-    scan[0][tid] = s;
+// Smallest thread index of the workgroup whose pred is true, or -1.
+__device__ int first_true256(bool pred, int *shi) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(pred);
+    if (lane == 0) shi[w] = m ? w * kWave + __ffsll((long long)m) - 1 : -1;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const double v = scan[cur][tid] + ((tid >= off) ? scan[cur][tid - off] : 0.0);
-        scan[cur ^ 1][tid] = v;
-        cur ^= 1;
-        __syncthreads();
+    int r = -1;
+    for (int q = 3; q >= 0; --q)
+        if (shi[q] >= 0) r = shi[q];
+    __syncthreads();
+    return r;
+}
+
+// Index in [lo, hi) of the first element whose inclusive running sum, added
+// to *run, passes target (the last one if none does), with *run advanced to
+// the exclusive running sum before it.  hi - lo may exceed 256 (chunks of 256).
+__device__ int64_t kpp_locate(const double *vals, int64_t lo, int64_t hi, double target, double *run,
+                              double *sh, int *shi) {
+    const int tid = threadIdx.x;
+    double base = *run;
+    for (int64_t c0 = lo; c0 < hi; c0 += 256) {
+        const int64_t i = c0 + tid;
+        const double v = (i < hi) ? vals[i] : 0.0;
+        double excl, tot;
+        const double incl = block_scan256(v, sh, &excl, &tot);
+        const int f = first_true256(i < hi && base + incl > target, shi);
+        if (f >= 0) {
+            if (tid == f) sh[4] = base + excl;
+            __syncthreads();
+            *run = sh[4];
+            __syncthreads();
+            return c0 + f;
+        }
+        base += tot;
     }
-    const double total = scan[cur][1023];
-    const double incl = scan[cur][tid];
-    const double excl = (tid > 0) ? scan[cur][tid - 1] : 0.0;
+    // rounding left the target at the very end
+    *run = base - vals[hi - 1];
+    return hi - 1;
+}
+
+// Seed t+1 from the sums: one workgroup of 256 threads.
+__global__ __launch_bounds__(256) void kpp_select(KppSums q, const float *dmin, int64_t n, double u,
+                                                  int32_t *seed_out) {
+    __shared__ double sh[8];
+    __shared__ int shi[4];
+    const int64_t nb = (n + kKppRows - 1) / kKppRows, ng = (n + kKppGroup - 1) / kKppGroup;
+    const int tid = threadIdx.x;
+    // ranges of groups, one per thread
+    const int64_t per = (ng + 255) / 256;
+    const int64_t g0 = min(ng, (int64_t)tid * per), g1 = min(ng, g0 + per);
+    double s = 0.0;
+    for (int64_t g = g0; g < g1; ++g) s += q.gsum[g];
+    double excl, total;
+    const double incl = block_scan256(s, sh, &excl, &total);
     if (!(total > 0.0)) {
-        if (tid == 0) seeds[t + 1] = (int32_t)min((int64_t)(u * (double)n), n - 1);
+        if (tid == 0) *seed_out = (int32_t)min((int64_t)(u * (double)n), n - 1);
         return;  // every row coincides with a seed
     }
     const double target = u * total;
-    // the first range whose inclusive sum passes the target (the last one if
-    // rounding leaves the target at the very end)
-    const bool mine = (incl > target && excl <= target) || (tid == 1023 && incl <= target);
-    if (!mine) return;
-    double run = excl;
-    int64_t b = b0;
-    while (b < b1 - 1 && run + bsum[b] <= target) run += bsum[b++];
-    int64_t pick = -1;
-    for (int64_t r = b * kKppRows; r < min(n, (b + 1) * kKppRows); ++r) {
-        run += (double)dmin[r];
-        if (run > target) {
-            pick = r;
-            break;
+    int r = first_true256(g0 < g1 && incl > target, shi);
+    if (r < 0) r = (int)((ng - 1) / per);  // the last non-empty range
+    if (tid == r) sh[4] = excl;
+    __syncthreads();
+    double run = sh[4];
+    __syncthreads();
+    const int64_t rg0 = (int64_t)r * per, rg1 = min(ng, rg0 + per);
+    const int64_t g = kpp_locate(q.gsum, rg0, rg1, target, &run, sh, shi);
+    const int64_t b = kpp_locate(q.bsum, g * kKppPerGroup, min(nb, (g + 1) * kKppPerGroup), target,
+                                 &run, sh, shi);
+    if (tid == 0) {
+        const int64_t r1 = min(n, (b + 1) * kKppRows);
+        int64_t row = r1 - 1;
+        for (int64_t i = b * kKppRows; i < r1; ++i) {
+            run += (double)dmin[i];
+            if (run > target) {
+                row = i;
+                break;
+            }
+        }
+        *seed_out = (int32_t)row;
+    }
+}
+
+// Block and group sums of the calling workgroup (thread i holds the updated
+// dmin of row blockIdx.x * kKppGroup + i, 0 past n).
+__device__ void kpp_sums(double v, int64_t n, const KppSums &q) {
+    __shared__ double sh[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t row = (int64_t)blockIdx.x * kKppGroup + tid;
+    const int g = lane & ~(kKppRows - 1);
+    const double v0 = __shfl(v, g, kWave), v1 = __shfl(v, g + 1, kWave);
+    const double v2 = __shfl(v, g + 2, kWave), v3 = __shfl(v, g + 3, kWave);
+    const double bs = (v0 + v1) + (v2 + v3);
+    const bool head = (lane & (kKppRows - 1)) == 0;
+    if (head && row < n) q.bsum[row / kKppRows] = bs;
+    const double ws = wave_sum(head ? bs : 0.0);
+    if (lane == 0) sh[w] = ws;
+    __syncthreads();
+    if (tid == 0) q.gsum[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// dmin_i = min over seeds 0..t of |F_i - F_seed|^2.  Wave w of a workgroup
+// takes rows 64w .. 64w+63 of its group, kKppPass at a time (all their loads
+// issued together), each row's squared distance summed over 16-byte slices
+// (lane l: columns 4l + 256j ..) and then across the wave.
+constexpr int kKppPass = 16;
+
+__global__ __launch_bounds__(256) void kpp_update(const float *F, int64_t n, int64_t f, int64_t ldf,
+                                                  int vec, const int32_t *seeds, int t, float *dmin,
+                                                  KppSums q) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kKppGroup + 64 * w;
+    const float *c = F + (int64_t)seeds[t] * ldf;
+    float mine = 0.f;
+    for (int p = 0; p < kWave / kKppPass; ++p) {
+        float d[kKppPass];
+#pragma unroll
+        for (int j = 0; j < kKppPass; ++j) d[j] = 0.f;
+        for (int64_t c0 = 0; c0 < f; c0 += 4 * kWave) {
+            const int64_t col = c0 + 4 * lane;
+            f32x4 cv = {0.f, 0.f, 0.f, 0.f};
+            const bool full = vec && col + 3 < f;
+            if (full) {
+                cv = *reinterpret_cast<const f32x4 *>(c + col);
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (col + e < f) cv[e] = c[col + e];
+            }
+            f32x4 xv[kKppPass];
+#pragma unroll
+            for (int j = 0; j < kKppPass; ++j) {
+                const int64_t row = r0 + kKppPass * p + j;
+                xv[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (row >= n) continue;
+                const float *x = F + row * ldf + col;
+                if (full) {
+                    xv[j] = *reinterpret_cast<const f32x4 *>(x);
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (col + e < f) xv[j][e] = x[e];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kKppPass; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float df = xv[j][e] - cv[e];
+                    d[j] = fmaf(df, df, d[j]);
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < kKppPass; ++j) {
+            const float sj = wave_sum(d[j]);
+            if (lane == kKppPass * p + j) mine = sj;
         }
     }
-    if (pick < 0) pick = min(n, (b + 1) * kKppRows) - 1;
-    seeds[t + 1] = (int32_t)pick;
+    const int64_t row = r0 + lane;
+    double v = 0.0;
+    if (row < n) {
+        const float m = (t == 0) ? mine : fminf(dmin[row], mine);
+        dmin[row] = m;
+        v = (double)m;
+    }
+    kpp_sums(v, n, q);
 }
 
 // ---------------------------------------------------------------- seeding on K
@@ -300,26 +431,22 @@ __device__ __forceinline__ float kentry(const uint16_t *K, int64_t idx) {
     return __uint_as_float((uint32_t)K[idx] << 16);
 }
 
-// dmin_i = min over seeds 0..t of the distance; block sums of kKppRows
-// consecutive rows in the same pairwise order as kpp_update.
+// dmin_i = min over seeds 0..t of the distance, one thread per row; the sums
+// as for the feature rows.
 template <typename T>
 __global__ __launch_bounds__(256) void kkpp_update(const T *K, int64_t ldk, const float *diag,
                                                    int64_t n, const int32_t *seeds, int t,
-                                                   float *dmin, double *bsum) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+                                                   float *dmin, KppSums q) {
+    const int64_t i = (int64_t)blockIdx.x * kKppGroup + threadIdx.x;
     const int64_t sd = seeds[t];
-    float m = 0.f;
+    double v = 0.0;
     if (i < n) {
         const float d = fmaxf(diag[i] + diag[sd] - 2.0f * kentry(K, sd * ldk + i), 0.0f);
-        m = (t == 0) ? d : fminf(dmin[i], d);
+        const float m = (t == 0) ? d : fminf(dmin[i], d);
         dmin[i] = m;
+        v = (double)m;
     }
-    const double v = (double)m;
-    const int lane = threadIdx.x & 63;
-    const int g = lane & ~(kKppRows - 1);
-    const double v0 = __shfl(v, g, kWave), v1 = __shfl(v, g + 1, kWave);
-    const double v2 = __shfl(v, g + 2, kWave), v3 = __shfl(v, g + 3, kWave);
-    if ((lane & (kKppRows - 1)) == 0 && i < n) bsum[i / kKppRows] = (v0 + v1) + (v2 + v3);
+    kpp_sums(v, n, q);
 }
 
 // label_i = index of the nearest seed (lowest on ties)
@@ -381,6 +508,7 @@ extern "C" size_t kkm_feature_kmeanspp_workspace_bytes(int64_t n, int64_t f, int
     Carver c(nullptr);
     c.take<float>((size_t)n);                                  // dmin
     c.take<double>((size_t)((n + kKppRows - 1) / kKppRows));   // block sums
+    c.take<double>((size_t)((n + kKppGroup - 1) / kKppGroup)); // group sums
     c.take<float>((size_t)(k * f));                            // seed rows
     c.take<float>((size_t)k);                                  // their norms
     c.take<float>((size_t)n);                                  // row norms
@@ -412,8 +540,10 @@ extern "C" kkm_status kkm_feature_kmeanspp(const float *F, int64_t n, int64_t f,
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
     float *dmin = c.take<float>((size_t)n);
-    const int64_t nb = (n + kKppRows - 1) / kKppRows;
-    double *bsum = c.take<double>((size_t)nb);
+    const int64_t ng = (n + kKppGroup - 1) / kKppGroup;
+    KppSums q;
+    q.bsum = c.take<double>((size_t)((n + kKppRows - 1) / kKppRows));
+    q.gsum = c.take<double>((size_t)ng);
     float *C = c.take<float>((size_t)(k * f));
     float *cn = c.take<float>((size_t)k);
     float *fn = c.take<float>((size_t)n);
@@ -423,11 +553,12 @@ extern "C" kkm_status kkm_feature_kmeanspp(const float *F, int64_t n, int64_t f,
     int64_t *changed = c.take<int64_t>(1);
     const int64_t first = (int64_t)(uniforms[0] * (double)n);
     hipLaunchKernelGGL(fill_one_i32, dim3(1), dim3(1), 0, s, seeds, (int32_t)(first < n ? first : n - 1));
+    const int vec = ((ldf & 3) == 0) && ((reinterpret_cast<uintptr_t>(F) & 15) == 0);
     for (int32_t t = 0; t + 1 < k; ++t) {
-        hipLaunchKernelGGL(kpp_update, dim3((unsigned)nb), dim3(256), 0, s, F, n, f, ldf, seeds, t,
-                           dmin, bsum);
-        hipLaunchKernelGGL(kpp_select, dim3(1), dim3(1024), 0, s, bsum, nb, dmin, n,
-                           uniforms[t + 1], seeds, t);
+        hipLaunchKernelGGL(kpp_update, dim3((unsigned)ng), dim3(256), 0, s, F, n, f, ldf, vec, seeds,
+                           t, dmin, q);
+        hipLaunchKernelGGL(kpp_select, dim3(1), dim3(256), 0, s, q, dmin, n, uniforms[t + 1],
+                           seeds + t + 1);
         KKM_HIP(hipGetLastError());
     }
     // labels: nearest seed (lowest index on ties), via the Lloyd assignment
@@ -461,8 +592,9 @@ extern "C" kkm_status kkm_feature_kmeanspp(const float *F, int64_t n, int64_t f,
 extern "C" size_t kkm_kernel_kmeanspp_workspace_bytes(int64_t n, int32_t k) {
     if (n < 1 || k < 1) return 0;
     Carver c(nullptr);
-    c.take<float>((size_t)n);                                 // dmin
-    c.take<double>((size_t)((n + kKppRows - 1) / kKppRows));  // block sums
+    c.take<float>((size_t)n);                                   // dmin
+    c.take<double>((size_t)((n + kKppRows - 1) / kKppRows));    // block sums
+    c.take<double>((size_t)((n + kKppGroup - 1) / kKppGroup));  // group sums
     return c.bytes();
 }
 
@@ -498,22 +630,22 @@ extern "C" kkm_status kkm_kernel_kmeanspp(const void *K, int32_t k_store, int64_
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
     float *dmin = c.take<float>((size_t)n);
-    const int64_t nb = (n + kKppRows - 1) / kKppRows;
-    double *bsum = c.take<double>((size_t)nb);
+    KppSums q;
+    q.bsum = c.take<double>((size_t)((n + kKppRows - 1) / kKppRows));
+    q.gsum = c.take<double>((size_t)((n + kKppGroup - 1) / kKppGroup));
     const int64_t first = (int64_t)(uniforms[0] * (double)n);
     hipLaunchKernelGGL(fill_one_i32, dim3(1), dim3(1), 0, s, seeds,
                        (int32_t)(first < n ? first : n - 1));
-    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    const dim3 g((unsigned)((n + kKppGroup - 1) / kKppGroup)), b(256);
     for (int32_t t = 0; t + 1 < k; ++t) {
         if (k_store == KKM_F32)
             hipLaunchKernelGGL(kkpp_update<float>, g, b, 0, s, static_cast<const float *>(K), ldk,
-                               diagK, n, seeds, t, dmin, bsum);
+                               diagK, n, seeds, t, dmin, q);
         else
             hipLaunchKernelGGL(kkpp_update<uint16_t>, g, b, 0, s,
-                               static_cast<const uint16_t *>(K), ldk, diagK, n, seeds, t, dmin,
-                               bsum);
-        hipLaunchKernelGGL(kpp_select, dim3(1), dim3(1024), 0, s, bsum, nb, dmin, n,
-                           uniforms[t + 1], seeds, t);
+                               static_cast<const uint16_t *>(K), ldk, diagK, n, seeds, t, dmin, q);
+        hipLaunchKernelGGL(kpp_select, dim3(1), dim3(256), 0, s, q, dmin, n, uniforms[t + 1],
+                           seeds + t + 1);
         KKM_HIP(hipGetLastError());
     }
     const size_t lds = sizeof(int32_t) * (size_t)k;
@@ -567,7 +699,7 @@ extern "C" kkm_status kkm_feature_lloyd(const float *F, int64_t n, int64_t f, in
     int32_t herr = 0;
     for (; t < max_iter; ++t) {
         KKM_TRY(vcsr_build(w.lab[cur], n, k, w.blk_hist, w.blk_bad, w.err, w.counts, w.perm,
-                           w.offsets, w.counts_out, w.changed, w.ticket, s));
+                           w.offsets, w.counts_out, w.changed, s));
         if (t == 0) {
             KKM_HIP(hipMemcpyAsync(&herr, w.err, sizeof herr, hipMemcpyDeviceToHost, s));
             KKM_HIP(hipStreamSynchronize(s));
