@@ -176,6 +176,86 @@ def warm_labels(kkm, w, params, Xd, seed):
     return best[1], cheap
 
 
+def learned_c5_leg(kkm, torch, dev):
+    """The learned warm start on its own workload: phi_theta trained on 10^7
+    kernel values of the 32-component mixture in R^128, then fresh n=100000
+    draws, k=32: plain FP32 from random labels against the BF16 form from the
+    learned warm start, both to convergence, and the FP32 form converged from
+    the same warm labels as the judge of the result (ARI)."""
+    import numpy as np
+
+    import datagen
+    w = datagen.WORKLOADS["learned100k"]
+    X, truth = w.points()
+    Xd = torch.from_numpy(X).to(dev)
+    ld = torch.from_numpy(w.labels0()).to(dev)
+    n = w.n
+    params, train_rep = train_feature_map(kkm, torch, w, dev)
+    K = kkm.alloc_kernel_matrix(n, kkm.F32, dev)
+    lab = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def plain_run():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, max_iter=w.max_iter, check_convergence=True,
+                           K_ws=K, labels_out=lab)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    plain_run()
+    pr = [plain_run() for _ in range(3)]
+    plain_s = float(np.median([x[0] for x in pr]))
+    rp = pr[-1][1]
+    plain_labels = lab.cpu().numpy()
+    useed = w.label_seed + 30003
+    warm, _ = warm_labels(kkm, w, params, Xd, useed)
+    ref = kkm.kkm_fit_ex(Xd, w.k, warm, w.kernel, w.gamma, max_iter=w.max_iter, check_convergence=True,
+                         K_ws=K, labels_out=lab)
+    ref_labels = lab.cpu().numpy()
+    del K
+    torch.cuda.empty_cache()
+    K16 = kkm.alloc_kernel_matrix(n, kkm.BF16, dev)
+    lab16 = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def learned_run():
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        wl, ch = warm_labels(kkm, w, params, Xd, useed)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        r = kkm.kkm_fit_ex(Xd, w.k, wl, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
+                           max_iter=w.max_iter, check_convergence=True, K_ws=K16, labels_out=lab16)
+        torch.cuda.synchronize()
+        return time.perf_counter() - ta, tb - ta, ch, r
+
+    learned_run()
+    lr = [learned_run() for _ in range(3)]
+    secs = float(np.median([x[0] for x in lr]))
+    _, _, ch, r = lr[-1]
+    ml = lab16.cpu().numpy()
+    del K16
+    torch.cuda.empty_cache()
+    rec = {
+        "workload": "learned100k: fresh draws n=%d of the 32-component mixture in R^%d (sigma 0.5), "
+                    "k=%d, gaussian gamma=1/%d" % (n, w.d, w.k, w.d),
+        "training": train_rep,
+        "plain_fp32": {"seconds": plain_s, "iters": rp["iters"], "objective": rp["objective"],
+                       "gram_ms": rp["times_ms"][0], "ari_vs_truth": ari(plain_labels, truth)},
+        "mixed_learned": {"seconds": secs, "warm_start_seconds": float(np.median([x[1] for x in lr])),
+                          "cheap_iters": ch, "exact_iters": r["iters"], "objective": r["objective"],
+                          "gram_ms": r["times_ms"][0], "ari_vs_truth": ari(ml, truth),
+                          "ari_vs_fp32_from_same_warm_start": ari(ml, ref_labels)},
+        "fp32_from_warm_start": {"iters": ref["iters"], "objective": ref["objective"]},
+        "exact_iters_saved": rp["iters"] - r["iters"],
+        "objective_rel_gap_vs_plain": (r["objective"] - rp["objective"]) / abs(rp["objective"]),
+        "speedup_time_to_converge_vs_plain": plain_s / secs,
+    }
+    log("learned100k: plain %.3f s (%d iters, J %.2f), mixed+learned %.3f s (%d cheap + %d exact, J %.2f), "
+        "ARI vs FP32 from same start %.4f" % (plain_s, rp["iters"], rp["objective"], secs, ch, r["iters"],
+                                              r["objective"], rec["mixed_learned"]["ari_vs_fp32_from_same_warm_start"]))
+    return rec
+
+
 def batched_leg(kkm, torch, dev, iters):
     """The batched form: 512 uneven Gaussian-mixture problems, BF16 Gram, FP32 K."""
     import numpy as np
@@ -308,6 +388,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="run only the learned warm start on its n=100000, k=32 workload")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched form and print its record")
     ap.add_argument("--gram-shapes", action="store_true",
@@ -331,6 +413,9 @@ def main():
     if args.gram_shapes:
         print(json.dumps({"gram_shapes": gram_shapes(kkm, torch, torch.device("cuda:0"))}),
               flush=True)
+        return
+    if args.learned_only:
+        print(json.dumps(learned_c5_leg(kkm, torch, torch.device("cuda:0"))), flush=True)
         return
     if args.batched_only:
         print(json.dumps(batched_leg(kkm, torch, torch.device("cuda:0"), args.iters or 30)),
@@ -503,6 +588,7 @@ def main():
         del K
     torch.cuda.empty_cache()
     batched = None if args.no_batched else batched_leg(kkm, torch, dev, iters)
+    learned_c5 = None if (args.no_learned or args.no_converge) else learned_c5_leg(kkm, torch, dev)
 
     out = {
         "metric": METRIC,
@@ -526,6 +612,7 @@ def main():
         "plain_fp32_to_convergence": plain,
         "mixed_learned_to_convergence": learned,
         "batched": batched,
+        "learned_warm_start_100k": learned_c5,
         "roofline": roof,
         "roofline_gram": roof_g,
         "cpu_baseline": None,

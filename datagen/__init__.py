@@ -166,6 +166,10 @@ WORKLOADS = {
     "rings": Workload("rings", 1000, 16, 4, GAUSS, 1.0, 0.0, 1, 50, True, 1, 101),
     "mnist_like": Workload("mnist_like", 60000, 784, 10, POLY, 1.0, 1.0, 2, 30, False, 2, 102),
     "gmm200k": Workload("gmm200k", 200000, 1024, 64, GAUSS, 1.0 / 1024, 0.0, 1, 30, False, 3, 103),
+    # the learned warm-start test set: fresh draws of the 32-component mixture
+    # in R^128 (sigma 0.5) that the feature network is trained on
+    "learned100k": Workload("learned100k", 100000, 128, 32, GAUSS, 1.0 / 128, 0.0, 1, 300, True, 5,
+                            105),
 }
 
 
