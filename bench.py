@@ -46,12 +46,12 @@ BF16_MFMA_PEAK_TFS = 2500.0
 # recorded value; otherwise the traffic is reported as null.
 TRAFFIC = {
     "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
-                       "sha256": "82b68ad40f6c8896156e91267981380c24f07740520d8327b9ec14472f2eec97",
-                       "n": 200000, "fetch_kib": 78169376.8, "write_kib": 85549.5,
+                       "sha256": "5dfa764ff32bcad8404bb7b0d925b865fc7dfd0af7fedd260eee0ae69eda4208",
+                       "n": 200000, "fetch_kib": 78169238.1, "write_kib": 85551.3,
                        "fetch_scale": 1.9999, "write_scale": 1.0},
     "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_tile.h", "csrc/kkm_common.h"],
-                      "sha256": "be9099a4a94dbd1dad73499dd12e336cb2c2bcc7f2f31bef1e912ce26f638edc",
-                      "n": 200000, "fetch_kib": 167039190.4, "write_kib": 156250901.8,
+                      "sha256": "0495d6dbc5eeb0508091ec838cdce9b1620d2ad1c5defc5c5c899e81f2f85226",
+                      "n": 200000, "fetch_kib": 162599214.9, "write_kib": 156250891.9,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }
 
