@@ -102,8 +102,17 @@ size_t kkm_gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec);
  * the diagonal only and stores each value at (i, j) and (j, i) (the SYRK
  * work); KKM_GRAM_FULL multiplies every tile of the square, each storing its
  * own block (the GEMM work, twice the flops, one store per value).  Both give
- * the same, exactly symmetric K. */
-typedef enum { KKM_GRAM_TRIANGLE = 0, KKM_GRAM_FULL = 1 } kkm_gram_shape;
+ * the same, exactly symmetric K.  The triangle uses 128 x 128 tiles
+ * (KKM_GRAM_TRIANGLE, KKM_GRAM_TRIANGLE_128); KKM_GRAM_TRIANGLE_256 asks for
+ * 256 x 256 tiles with a BF16 or FP8 product (half the operand traffic per
+ * MFMA, one workgroup per CU; slower on MI355X in every case measured, kept
+ * selectable).  Every shape gives the same K bit for bit. */
+typedef enum {
+    KKM_GRAM_TRIANGLE = 0,
+    KKM_GRAM_FULL = 1,
+    KKM_GRAM_TRIANGLE_128 = 2,
+    KKM_GRAM_TRIANGLE_256 = 3
+} kkm_gram_shape;
 
 /* kkm_gram_ex — kkm_gram with the tile shape chosen (kkm_gram uses
  * KKM_GRAM_TRIANGLE).  KKM_ERR_ARG for an unknown shape. */

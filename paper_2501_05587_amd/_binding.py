@@ -183,13 +183,15 @@ def iterate_workspace_bytes(n: int, k: int) -> int:
     return int(lib().kkm_iterate_workspace_bytes(n, k))
 
 
-GRAM_TRIANGLE, GRAM_FULL = 0, 1
+GRAM_TRIANGLE, GRAM_FULL, GRAM_TRIANGLE_128, GRAM_TRIANGLE_256 = 0, 1, 2, 3
 
 
 def kkm_gram(X, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram_prec=F32, k_store=F32,
              K=None, diagK=None, ws=None, shape=GRAM_TRIANGLE):
     """K = kappa(X X^T) and diag(K) on the GPU.  Returns (K, diagK).  shape:
-    GRAM_TRIANGLE (upper-triangle tiles, mirrored stores) or GRAM_FULL (every tile)."""
+    GRAM_TRIANGLE (upper-triangle 128 x 128 tiles, mirrored stores; also
+    GRAM_TRIANGLE_128), GRAM_FULL (every tile), or GRAM_TRIANGLE_256 (the
+    triangle in 256 x 256 tiles for a BF16 / FP8 product)."""
     _dev(X, torch.float32, "X", 2)
     n, d, ldx = _rows(X, "X")
     if K is None:

@@ -206,7 +206,8 @@ extern "C" kkm_status kkm_gram_ex(const float *X, int64_t n, int64_t d, int64_t 
                   (long long)n, (long long)d, (long long)ldx, (long long)ldk);
         return KKM_ERR_ARG;
     }
-    if (shape != KKM_GRAM_TRIANGLE && shape != KKM_GRAM_FULL) {
+    if (shape != KKM_GRAM_TRIANGLE && shape != KKM_GRAM_FULL && shape != KKM_GRAM_TRIANGLE_128 &&
+        shape != KKM_GRAM_TRIANGLE_256) {
         set_error("kkm_gram: unknown shape %d", shape);
         return KKM_ERR_ARG;
     }

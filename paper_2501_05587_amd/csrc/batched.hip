@@ -418,7 +418,7 @@ void make_plan(const kkm_instance *inst, int32_t count, int32_t gram_prec, int32
         e.n = q.n;
         e.ldk = in.ldk;
         e.kernel = q.kernel_type;
-        e.gamma = (float)q.gamma;
+        e.gamma = epi_gamma(q.kernel_type, q.gamma);
         e.coef0 = (float)q.coef0;
         e.degree = q.degree;
         e.nrm = p.h_rtab[b].nrm;

@@ -13,12 +13,7 @@ constexpr int TM = 64, TK = 32, TLD = TK + 1;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ __bf16 to_bf16(float f) {
-    const uint32_t u = __float_as_uint(f);
-    const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-    const uint16_t h = (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? ((u >> 16) | 0x40) : r);
-    __bf16 b;
-    __builtin_memcpy(&b, &h, 2);
-    return b;
+    return (__bf16)f;  // round to nearest even (one hardware conversion on gfx950)
 }
 
 __device__ __forceinline__ float gelu(float z) {

@@ -49,6 +49,14 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_lowp_mfma(LowpTile a, TileOr
     lowp_tile<PREC, OUT, FULL>(a, bi, bj, lds);
 }
 
+template <int PREC, typename OUT>
+__global__ __launch_bounds__(GTHREADS, 1) void gram_lowp_mfma256(LowpTile a, TileOrder o) {
+    __shared__ __attribute__((aligned(16))) LowpLds256 lds;
+    int64_t bi, bj;
+    if (!tile_of_block(o, bi, bj)) return;
+    lowp_tile256<PREC, OUT>(a, bi, bj, lds);
+}
+
 // ---------------------------------------------------------------- prologues
 
 // Squared row norms ||x_i||^2 for the Gaussian (FP32 product): one wave per row.
@@ -71,6 +79,19 @@ __global__ __launch_bounds__(256) void quantize_rows(const float *X, int64_t n, 
     const int64_t eb = (PREC == KKM_BF16) ? 2 : 1;
     quantize_row<PREC>(X + row * ldx, d, dpad, Xq + row * dpad * eb, nrm + row, scale + row,
                        threadIdx.x & 63);
+}
+
+void lowp256_dispatch(int32_t gram_prec, int32_t k_store, dim3 g, dim3 b, const LowpTile &a,
+                      const TileOrder &order, hipStream_t stream) {
+    if (gram_prec == KKM_BF16 && k_store == KKM_F32)
+        hipLaunchKernelGGL((gram_lowp_mfma256<KKM_BF16, float>), g, b, 0, stream, a, order);
+    else if (gram_prec == KKM_BF16)
+        hipLaunchKernelGGL((gram_lowp_mfma256<KKM_BF16, uint16_t>), g, b, 0, stream, a, order);
+    else if (k_store == KKM_F32)
+        hipLaunchKernelGGL((gram_lowp_mfma256<KKM_FP8_ROWSCALED, float>), g, b, 0, stream, a, order);
+    else
+        hipLaunchKernelGGL((gram_lowp_mfma256<KKM_FP8_ROWSCALED, uint16_t>), g, b, 0, stream, a,
+                           order);
 }
 
 template <bool FULL>
@@ -124,7 +145,7 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
     e.n = n;
     e.ldk = ldk;
     e.kernel = kernel;
-    e.gamma = (float)gamma;
+    e.gamma = epi_gamma(kernel, gamma);
     e.coef0 = (float)coef0;
     e.degree = degree;
     e.nrm = nrm;
@@ -135,7 +156,11 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
     e.vec_k = (k_store == KKM_F32) ? (((ldk % 4) == 0) && ((kaddr & 15) == 0))
                                    : (((ldk % 4) == 0) && ((kaddr & 7) == 0));
     const bool full = (shape == KKM_GRAM_FULL);
-    const TileOrder order = tile_order(n, group_log2(d, gram_prec), full);
+    // 256 x 256 tiles only on request: measured slower on MI355X at every n and
+    // d tried (one workgroup per CU leaves the epilogue and the operand-load
+    // latency of a tile without another tile to hide behind)
+    const bool big = gram_prec != KKM_F32 && shape == KKM_GRAM_TRIANGLE_256;
+    const TileOrder order = tile_order(n, group_log2(d, gram_prec), full, big ? GB : GM);
     const int64_t grid = order.per_xcd * 8;
     if (grid > 0x7fffffff) {
         set_error("kkm_gram: n=%lld needs more than 2^31 tiles", (long long)n);
@@ -188,7 +213,9 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
     if (gram_prec == KKM_FP8_ROWSCALED) a.e.scale = scale;
     const TimedSpan span = timing_begin(TK_GRAM, stream);
     const dim3 g((unsigned)grid), b(GTHREADS);
-    if (!full)
+    if (big)
+        lowp256_dispatch(gram_prec, k_store, g, b, a, order, stream);
+    else if (!full)
         lowp_dispatch<false>(gram_prec, k_store, g, b, a, order, stream);
     else
         lowp_dispatch<true>(gram_prec, k_store, g, b, a, order, stream);

@@ -5,6 +5,8 @@
 // input type).  Internal to the library.
 #pragma once
 
+#include <type_traits>
+
 #include "kkm_common.h"
 
 namespace kkm {
@@ -16,10 +18,11 @@ constexpr int GTHREADS = 256; // 4 waves as 2 x 2, each owns a 64 x 64 sub-tile
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    // round to nearest even on the dropped 16 bits; a NaN stays a (quiet) NaN
-    const uint32_t u = __float_as_uint(f);
-    const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-    return (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? ((u >> 16) | 0x40) : r);
+    // round to nearest even (one hardware conversion on gfx950); a NaN stays a NaN
+    const __bf16 h = (__bf16)f;
+    uint16_t u;
+    __builtin_memcpy(&u, &h, 2);
+    return u;
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -28,7 +31,7 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 struct Epi {
     int64_t n, ldk;
     int kernel;
-    float gamma, coef0;
+    float gamma, coef0;  // Gaussian: gamma * log2(e), see epi_gamma
     int degree;
     const float *nrm;    // squared norms (Gaussian)
     const float *scale;  // per-row scales (FP8), else null
@@ -37,11 +40,18 @@ struct Epi {
     int vec_k;           // K rows aligned for 4-element stores
 };
 
+// The kernel's gamma as the epilogue takes it: for the Gaussian, gamma log2(e)
+// (rounded once, from double), so that exp(-gamma s) = 2^(-gamma log2(e) s) is
+// one multiply and the hardware base-2 exponential.
+inline float epi_gamma(int kernel, double gamma) {
+    return (float)(kernel == KKM_GAUSS ? gamma * 1.4426950408889634074 : gamma);
+}
+
 __device__ __forceinline__ float kappa_from_dot(float b, float ni, float nj, int kernel,
                                                 float gamma, float coef0, int degree) {
     if (kernel == KKM_GAUSS) {
         float sq = fmaxf(ni + nj - 2.0f * b, 0.0f);
-        return expf(-gamma * sq);
+        return __builtin_amdgcn_exp2f(-gamma * sq);
     }
     if (kernel == KKM_POLY) {
         float t = fmaf(gamma, b, coef0);
@@ -69,10 +79,10 @@ template <> struct Store<uint16_t> {
         static_cast<uint16_t *>(K)[idx] = f32_to_bf16(v);
     }
     static __device__ __forceinline__ void four(void *K, int64_t idx, const float v[4]) {
-        uint2 w;
-        w.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
-        w.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
-        *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(K) + idx) = w;
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        const f32x4 f = {v[0], v[1], v[2], v[3]};
+        *reinterpret_cast<bf16x4 *>(static_cast<uint16_t *>(K) + idx) =
+            __builtin_convertvector(f, bf16x4);
     }
 };
 
@@ -80,6 +90,39 @@ template <> struct Store<uint16_t> {
 // spreads the 16-byte accesses of lanes holding consecutive rows over all banks.
 constexpr int TS = GM + 4;
 constexpr size_t EPI_LDS_BYTES = sizeof(float) * GM * TS;
+
+// Rows r = 0..127 of the staged tile T to K[row0 + r][col0 .. col0 + 127],
+// skipping rows and columns at or past n: each thread stores 4 columns of
+// every eighth row, reading eight rows from LDS before it waits.
+template <typename OUT>
+__device__ __forceinline__ void store_rows(const Epi &e, const float *T, int64_t row0, int64_t col0) {
+    const int tid = threadIdx.x;
+    const int c4 = (tid & 31) * 4;
+    const int64_t gj0 = col0 + c4;
+    if (gj0 >= e.n) return;
+    const bool vec = e.vec_k && gj0 + 3 < e.n;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        f32x4 w[8];
+#pragma unroll
+        for (int it = 0; it < 8; ++it)
+            w[it] = *reinterpret_cast<const f32x4 *>(T + ((tid >> 5) + 8 * (8 * h + it)) * TS + c4);
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int64_t gi = row0 + (tid >> 5) + 8 * (8 * h + it);
+            if (gi >= e.n) continue;
+            const float v[4] = {w[it][0], w[it][1], w[it][2], w[it][3]};
+            const int64_t idx = gi * e.ldk + gj0;
+            if (vec) {
+                Store<OUT>::four(e.K, idx, v);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (gj0 + r < e.n) Store<OUT>::one(e.K, idx + r, v[r]);
+            }
+        }
+    }
+}
 
 // The squared norms (and FP8 row scales) of a tile's 128 rows and 128
 // columns, staged in LDS when the tile starts so that their loads overlap the
@@ -114,8 +157,6 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
                                          int64_t n0, bool diag_tile, int wr, int wc, int lane,
                                          float *T, const float *rn, const float *rs) {
     const int half = lane >> 5, l32 = lane & 31;
-    const int tid = threadIdx.x;
-    const int c4 = (tid & 31) * 4;
     if constexpr (FULL) {
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
@@ -143,21 +184,7 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
                 }
             }
         __syncthreads();
-        // K[m0 + ii][n0 .. n0 + 127]; rows and columns may pass n
-        for (int ii = tid >> 5; ii < GM; ii += GTHREADS / 32) {
-            const int64_t gi = m0 + ii, gj0 = n0 + c4;
-            if (gi >= e.n || gj0 >= e.n) continue;
-            const f32x4 w = *reinterpret_cast<const f32x4 *>(T + ii * TS + c4);
-            const float v[4] = {w[0], w[1], w[2], w[3]};
-            const int64_t idx = gi * e.ldk + gj0;
-            if (e.vec_k && gj0 + 3 < e.n) {
-                Store<OUT>::four(e.K, idx, v);
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (gj0 + r < e.n) Store<OUT>::one(e.K, idx + r, v[r]);
-            }
-        }
+        store_rows<OUT>(e, T, m0, n0);  // rows and columns may pass n
         __syncthreads();
         return;
     }
@@ -185,20 +212,7 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
                 }
             }
         __syncthreads();
-        // K[n0 + jj][m0 .. m0 + 127]; off the diagonal m0 + 127 < n0 < n
-        for (int jj = tid >> 5; jj < GM; jj += GTHREADS / 32) {
-            const int64_t gj = n0 + jj;
-            if (gj >= e.n) break;
-            const f32x4 w = *reinterpret_cast<const f32x4 *>(T + jj * TS + c4);
-            const float v[4] = {w[0], w[1], w[2], w[3]};
-            const int64_t idx = gj * e.ldk + m0 + c4;
-            if (e.vec_k) {
-                Store<OUT>::four(e.K, idx, v);
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Store<OUT>::one(e.K, idx + r, v[r]);
-            }
-        }
+        store_rows<OUT>(e, T, n0, m0);  // K[n0 + jj][m0 ..]; off the diagonal m0 + 127 < n0
         __syncthreads();
         // as is: T[ii][jj]
 #pragma unroll
@@ -214,21 +228,7 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
                 }
             }
         __syncthreads();
-        // K[m0 + ii][n0 .. n0 + 127]: every row exists; columns may pass n
-        for (int ii = tid >> 5; ii < GM; ii += GTHREADS / 32) {
-            const int64_t gj0 = n0 + c4;
-            if (gj0 >= e.n) continue;
-            const f32x4 w = *reinterpret_cast<const f32x4 *>(T + ii * TS + c4);
-            const float v[4] = {w[0], w[1], w[2], w[3]};
-            const int64_t idx = (m0 + ii) * e.ldk + gj0;
-            if (e.vec_k && gj0 + 3 < e.n) {
-                Store<OUT>::four(e.K, idx, v);
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (gj0 + r < e.n) Store<OUT>::one(e.K, idx + r, v[r]);
-            }
-        }
+        store_rows<OUT>(e, T, m0, n0);  // K[m0 + ii][n0 ..]: every row exists; columns may pass n
         __syncthreads();
         return;
     }
@@ -269,6 +269,63 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
     __syncthreads();
 }
 
+// The off-diagonal epilogue for tiles whose accumulators must stay where the
+// product left them (the 256 x 256 tile holds all 256 accumulator registers
+// of a lane): kappa is computed for the transposed pass and again, from the
+// same accumulators with the same operations, for the pass as is.  Same
+// stores as the off-diagonal branch of `epilogue`; a diagonal tile goes
+// through `epilogue` (its diagonal branch only reads the accumulators).
+template <typename OUT>
+__device__ __forceinline__ void epilogue_keep(const Epi &e, f32x16 (&acc)[2][2], int64_t m0,
+                                              int64_t n0, bool diag_tile, int wr, int wc,
+                                              int lane, float *T, const float *rn,
+                                              const float *rs) {
+    if (diag_tile) {
+        epilogue<OUT, false>(e, acc, m0, n0, true, wr, wc, lane, T, rn, rs);
+        return;
+    }
+    const int half = lane >> 5, l32 = lane & 31;
+    auto kap = [&](int mi, int ni, int rg, int r, float nrm_j, float s_j) {
+        const int ii = wr * 64 + mi * 32 + 8 * rg + 4 * half + r;
+        float b = acc[mi][ni][4 * rg + r];
+        if (e.scale) b *= rs[ii] * s_j;
+        return kappa_from_dot(b, rn[ii], nrm_j, e.kernel, e.gamma, e.coef0, e.degree);
+    };
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) {
+            const int jj = wc * 64 + ni * 32 + l32;
+            const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
+#pragma unroll
+            for (int rg = 0; rg < 4; ++rg) {
+                const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+                const f32x4 w = {kap(mi, ni, rg, 0, nrm_j, s_j), kap(mi, ni, rg, 1, nrm_j, s_j),
+                                 kap(mi, ni, rg, 2, nrm_j, s_j), kap(mi, ni, rg, 3, nrm_j, s_j)};
+                *reinterpret_cast<f32x4 *>(T + jj * TS + ii0) = w;
+            }
+        }
+    __syncthreads();
+    store_rows<OUT>(e, T, n0, m0);  // K[n0 + jj][m0 ..]; off the diagonal m0 + 127 < n0
+    __syncthreads();
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) {
+            const int jj = wc * 64 + ni * 32 + l32;
+            const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
+#pragma unroll
+            for (int rg = 0; rg < 4; ++rg) {
+                const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) T[(ii0 + r) * TS + jj] = kap(mi, ni, rg, r, nrm_j, s_j);
+            }
+        }
+    __syncthreads();
+    store_rows<OUT>(e, T, m0, n0);  // K[m0 + ii][n0 ..]: every row exists; columns may pass n
+    __syncthreads();
+}
+
 // Upper-triangle tile t -> (bi, bj), bi <= bj, column by column.
 __device__ __forceinline__ void tile_coords(int64_t t, int64_t &bi, int64_t &bj) {
     int64_t j = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -293,9 +350,9 @@ struct TileOrder {
     int full;          // every tile of the square (else the upper triangle)
 };
 
-inline TileOrder tile_order(int64_t n, int lg, bool full = false) {
+inline TileOrder tile_order(int64_t n, int lg, bool full = false, int tile = GM) {
     TileOrder o;
-    o.nb = (n + GM - 1) / GM;
+    o.nb = (n + tile - 1) / tile;
     o.lg = lg;
     o.full = full;
     o.G = (o.nb + (int64_t(1) << lg) - 1) >> lg;
@@ -574,6 +631,156 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
     static_assert(sizeof(lds.op) >= EPI_LDS_BYTES, "epilogue tile does not fit");
     epilogue<OUT, FULL>(a.e, acc, m0, n0, bi == bj, wr, wc, lane,
                         reinterpret_cast<float *>(&lds.op[0][0][0]), lds.rn, lds.rs);
+}
+
+// ---------------------------------------------------------------- BF16 / FP8 product, 256 x 256 tiles
+//
+// For large problems: a 256 x 256 tile per workgroup of 256 threads (one
+// workgroup per CU).  Wave (wr, wc) holds, in each 128 x 128 quadrant (QR, QC)
+// of the tile, the same 64 x 64 sub-block it holds in a 128 x 128 tile, so one
+// k-step takes 4 A and 4 B fragments for 16 MFMAs (the 128 x 128 tile: 2 + 2
+// for 4), halving the operand traffic per MFMA from LDS and from L2.  Every
+// output element multiplies the same slabs in the same order as in the 128 x
+// 128 tile, so K is the same bit for bit.  The quadrants leave one by one
+// through the 128 x 128 epilogue; on a diagonal tile quadrant (1, 0) is the
+// mirror of quadrant (0, 1) and is not written.
+constexpr int GB = 2 * GM;
+
+struct LowpLds256 {
+    unsigned char op[2][2][GB * SLD];  // operand slabs, double-buffered
+    float rn[2 * GB], rs[2 * GB];      // [0, 256) rows m0.., [256, 512) rows n0..
+    float qn[2 * GM], qs[2 * GM];      // one quadrant's, in the epilogue's layout
+};
+
+template <int PREC, typename OUT>
+__device__ __forceinline__ void lowp_tile256(const LowpTile &a, int64_t bi, int64_t bj,
+                                             LowpLds256 &lds) {
+    const int64_t m0 = bi * GB, n0 = bj * GB;
+    const bool diag = (bi == bj);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int ld_row = tid >> 3;  // 8 threads x 16 bytes per row slab
+    const int ld_col = (tid & 7) * 16;
+
+    uint4 ra[8], rb[8];
+    auto gload = [&](int64_t slab) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t r1 = m0 + ld_row + 32 * u, r2 = n0 + ld_row + 32 * u;
+            ra[u] = make_uint4(0, 0, 0, 0);
+            rb[u] = make_uint4(0, 0, 0, 0);
+            if (r1 < a.e.n)
+                ra[u] = *reinterpret_cast<const uint4 *>(a.Xq + r1 * a.ldq_bytes + slab * SLAB + ld_col);
+            if (r2 < a.e.n)
+                rb[u] = *reinterpret_cast<const uint4 *>(a.Xq + r2 * a.ldq_bytes + slab * SLAB + ld_col);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            *reinterpret_cast<uint4 *>(&lds.op[buf][0][(ld_row + 32 * u) * SLD + ld_col]) = ra[u];
+            *reinterpret_cast<uint4 *>(&lds.op[buf][1][(ld_row + 32 * u) * SLD + ld_col]) = rb[u];
+        }
+    };
+
+    f32x16 acc[2][2][2][2];  // [QR][QC][mi][ni]
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[q >> 3][(q >> 2) & 1][(q >> 1) & 1][q & 1][r] = 0.f;
+
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int t = tid + 256 * h;
+        const int64_t g = (t < GB) ? m0 + t : n0 + (t - GB);
+        const bool in = g < a.e.n;
+        lds.rn[t] = (a.e.kernel == KKM_GAUSS && in) ? a.e.nrm[g] : 0.f;
+        lds.rs[t] = (a.e.scale && in) ? a.e.scale[g] : 1.f;
+    }
+    gload(0);
+    sstore(0);
+    __syncthreads();
+
+    // the k permutation of the 128 x 128 tile: MFMA s takes from lane half h
+    // the 16 bytes at 64h + 16s (bf16) or the 8 bytes at 64h + 8s (fp8)
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    for (int64_t kt = 0; kt < a.nslab; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < a.nslab) gload(kt + 1);
+        const unsigned char *As = lds.op[buf][0] + (wr * 64 + l32) * SLD + half * 64;
+        const unsigned char *Bs = lds.op[buf][1] + (wc * 64 + l32) * SLD + half * 64;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint4 av[2][2], bv[2][2];  // [Q][mi]
+#pragma unroll
+            for (int Q = 0; Q < 2; ++Q)
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi) {
+                    av[Q][mi] = *reinterpret_cast<const uint4 *>(As + (Q * GM + mi * 32) * SLD + 16 * q);
+                    bv[Q][mi] = *reinterpret_cast<const uint4 *>(Bs + (Q * GM + mi * 32) * SLD + 16 * q);
+                }
+            if constexpr (PREC == KKM_BF16) {
+#pragma unroll
+                for (int QR = 0; QR < 2; ++QR)
+#pragma unroll
+                    for (int QC = 0; QC < 2; ++QC)
+#pragma unroll
+                        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                            for (int ni = 0; ni < 2; ++ni) {
+                                bf16x8 x, y;
+                                __builtin_memcpy(&x, &av[QR][mi], 16);
+                                __builtin_memcpy(&y, &bv[QC][ni], 16);
+                                acc[QR][QC][mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    x, y, acc[QR][QC][mi][ni], 0, 0, 0);
+                            }
+            } else {
+#pragma unroll
+                for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+                    for (int QR = 0; QR < 2; ++QR)
+#pragma unroll
+                        for (int QC = 0; QC < 2; ++QC)
+#pragma unroll
+                            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                                for (int ni = 0; ni < 2; ++ni) {
+                                    const uint4 &p = av[QR][mi];
+                                    const uint4 &r = bv[QC][ni];
+                                    const long x = sub ? (long)(((uint64_t)p.w << 32) | p.z)
+                                                       : (long)(((uint64_t)p.y << 32) | p.x);
+                                    const long y = sub ? (long)(((uint64_t)r.w << 32) | r.z)
+                                                       : (long)(((uint64_t)r.y << 32) | r.x);
+                                    acc[QR][QC][mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(
+                                        x, y, acc[QR][QC][mi][ni], 0, 0, 0);
+                                }
+            }
+        }
+        if (kt + 1 < a.nslab) sstore(buf ^ 1);
+        __syncthreads();
+    }
+    static_assert(sizeof(lds.op) >= EPI_LDS_BYTES, "epilogue tile does not fit");
+    float *T = reinterpret_cast<float *>(&lds.op[0][0][0]);
+    // the quadrants one by one, with compile-time indices into acc (a loop
+    // too large to unroll would index it at run time and force it into memory)
+    auto quadrant = [&](auto qr, auto qc) {
+        constexpr int QR = decltype(qr)::value, QC = decltype(qc)::value;
+        const int64_t m0q = m0 + QR * GM, n0q = n0 + QC * GM;
+        if ((diag && QR > QC) || m0q >= a.e.n || n0q >= a.e.n) return;
+        lds.qn[tid] = (tid < GM) ? lds.rn[QR * GM + tid] : lds.rn[GB + QC * GM + (tid - GM)];
+        lds.qs[tid] = (tid < GM) ? lds.rs[QR * GM + tid] : lds.rs[GB + QC * GM + (tid - GM)];
+        __syncthreads();
+        epilogue_keep<OUT>(a.e, acc[QR][QC], m0q, n0q, diag && QR == QC, wr, wc, lane, T, lds.qn,
+                           lds.qs);
+    };
+    quadrant(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    quadrant(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
+    quadrant(std::integral_constant<int, 1>{}, std::integral_constant<int, 0>{});
+    quadrant(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{});
 }
 
 __device__ __forceinline__ float wave_max(float v) {

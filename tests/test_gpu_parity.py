@@ -237,3 +237,23 @@ def test_full_shape_equals_triangle(kkm, gp, ks, n, d):
         torch.cuda.synchronize()
         assert torch.equal(a, b), (gp, ks, kern)
         assert torch.equal(da, db)
+
+
+@pytest.mark.parametrize("gp,ks", [(1, 0), (1, 1), (2, 0), (2, 1)])
+@pytest.mark.parametrize("n,d", [(1, 3), (129, 33), (300, 100), (700, 256), (1100, 64), (2600, 200),
+                                 (513, 1030)])
+def test_256_tile_equals_128_tile(kkm, gp, ks, n, d):
+    """The BF16 / FP8 triangle in 256 x 256 tiles gives bit for bit the K and
+    diag(K) of the 128 x 128 tiles (same slabs, same order per entry); n from
+    one point to several tiles with ragged edges (2600 = 10 * 256 + 40), d
+    from one slab to 17 with a ragged last slab."""
+    import torch
+    X = np.random.default_rng(7 * n + d).normal(0, 1, (n, d)).astype(np.float32)
+    Xd = to_dev(X)
+    say("256 tile", n, d, gp, ks)
+    for kern, g, c0 in ((kkm.GAUSS, 1.0 / d, 0.0), (kkm.POLY, 0.1, 1.0), (kkm.LINEAR, 1.0, 0.0)):
+        a, da = kkm.kkm_gram(Xd, kern, g, c0, 2, gram_prec=gp, k_store=ks, shape=kkm.GRAM_TRIANGLE_128)
+        b, db = kkm.kkm_gram(Xd, kern, g, c0, 2, gram_prec=gp, k_store=ks, shape=kkm.GRAM_TRIANGLE_256)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), (gp, ks, kern, (a != b).sum().item())
+        assert torch.equal(da, db)
