@@ -28,6 +28,8 @@
 #include <numeric>
 #include <vector>
 
+#include <type_traits>
+
 #include "gram_tile.h"
 #include "iterate.h"
 
@@ -79,19 +81,16 @@ __global__ __launch_bounds__(256) void batch_prologue(const RowSrc *tab, const i
 
 // ---------------------------------------------------------------- 2. Gram
 
-union TileLds {
-    F32Lds f;
-    LowpLds q;
-};
-
 // Persistent: every workgroup pops chunks of kQueueChunk tiles until the
-// counter passes the tile total, so every wave reaches the exit.
+// counter passes the tile total, so every wave reaches the exit.  Two
+// workgroups per CU, double-buffered slabs (the persistent loop keeps more
+// state live than the single-problem kernel, which fits three).
 template <int PREC, typename OUT>
 __global__ __launch_bounds__(GTHREADS, 2) void batch_gram(const GramSrc *tab,
                                                           const int64_t *tile_start,
                                                           int32_t count,
                                                           unsigned long long *queue) {
-    __shared__ __attribute__((aligned(16))) TileLds lds;
+    __shared__ __attribute__((aligned(16))) std::conditional_t<PREC == KKM_F32, F32Lds, LowpLds<true>> lds;
     __shared__ long long next;
     const int64_t total = uniform_load(tile_start + count);
     for (;;) {
@@ -106,9 +105,9 @@ __global__ __launch_bounds__(GTHREADS, 2) void batch_gram(const GramSrc *tab,
             int64_t bi, bj;
             tile_coords(t - uniform_load(tile_start + b), bi, bj);
             if constexpr (PREC == KKM_F32)
-                f32_tile<OUT>(uniform_load(&tab[b].f), bi, bj, lds.f);
+                f32_tile<OUT>(uniform_load(&tab[b].f), bi, bj, lds);
             else
-                lowp_tile<PREC, OUT>(uniform_load(&tab[b].q), bi, bj, lds.q);
+                lowp_tile<PREC, OUT>(uniform_load(&tab[b].q), bi, bj, lds);
         }
     }
 }

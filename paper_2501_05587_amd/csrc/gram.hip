@@ -41,12 +41,13 @@ __global__ __launch_bounds__(GTHREADS, 2) void gram_f32_mfma(F32Tile a, TileOrde
 
 // ---------------------------------------------------------------- BF16 / FP8 product
 
+// One tile per workgroup, three workgroups per CU (single-buffered slabs).
 template <int PREC, typename OUT, bool FULL>
-__global__ __launch_bounds__(GTHREADS, 2) void gram_lowp_mfma(LowpTile a, TileOrder o) {
-    __shared__ __attribute__((aligned(16))) LowpLds lds;
+__global__ __launch_bounds__(GTHREADS, 3) void gram_lowp_mfma(LowpTile a, TileOrder o) {
+    __shared__ __attribute__((aligned(16))) LowpLds<false> lds;
     int64_t bi, bj;
     if (!tile_of_block(o, bi, bj)) return;
-    lowp_tile<PREC, OUT, FULL>(a, bi, bj, lds);
+    lowp_tile<PREC, OUT, FULL, false>(a, bi, bj, lds);
 }
 
 template <int PREC, typename OUT>

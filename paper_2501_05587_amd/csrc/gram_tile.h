@@ -89,12 +89,13 @@ template <> struct Store<uint16_t> {
 // Row stride (floats) of the tile staged in LDS by the epilogue: the pad
 // spreads the 16-byte accesses of lanes holding consecutive rows over all banks.
 constexpr int TS = GM + 4;
-constexpr size_t EPI_LDS_BYTES = sizeof(float) * GM * TS;
+// LDS the epilogue stages through: the whole tile, or half of it at a time
+constexpr size_t epi_lds_bytes(int halves) { return sizeof(float) * (GM / halves) * TS; }
 
-// Rows r = 0..127 of the staged tile T to K[row0 + r][col0 .. col0 + 127],
+// Rows r = 0..ROWS-1 of the staged tile T to K[row0 + r][col0 .. col0 + 127],
 // skipping rows and columns at or past n: each thread stores 4 columns of
 // every eighth row, reading eight rows from LDS before it waits.
-template <typename OUT>
+template <typename OUT, int ROWS = GM>
 __device__ __forceinline__ void store_rows(const Epi &e, const float *T, int64_t row0, int64_t col0) {
     const int tid = threadIdx.x;
     const int c4 = (tid & 31) * 4;
@@ -102,7 +103,7 @@ __device__ __forceinline__ void store_rows(const Epi &e, const float *T, int64_t
     if (gj0 >= e.n) return;
     const bool vec = e.vec_k && gj0 + 3 < e.n;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < ROWS / 64; ++h) {
         f32x4 w[8];
 #pragma unroll
         for (int it = 0; it < 8; ++it)
@@ -152,85 +153,195 @@ __device__ __forceinline__ void stage_norms(const Epi &e, int64_t m0, int64_t n0
 // each tile writes only its own block K[i][j], through `T` as is; a diagonal
 // tile also writes diag(K).  Tile (j, i) multiplies the same products in the
 // same order as tile (i, j), so K is still exactly symmetric.
-template <typename OUT, bool FULL>
+template <typename OUT, bool FULL, int HALVES = 1>
 __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int64_t m0,
                                          int64_t n0, bool diag_tile, int wr, int wc, int lane,
                                          float *T, const float *rn, const float *rs) {
+    static_assert(HALVES == 1 || HALVES == 2, "whole tile or halves");
+    constexpr int RH = GM / HALVES;  // rows of T staged at a time
     const int half = lane >> 5, l32 = lane & 31;
-    if constexpr (FULL) {
+    if constexpr (HALVES == 1) {
+        if constexpr (FULL) {
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+            for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni) {
-                const int jj = wc * 64 + ni * 32 + l32;
-                const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
+                for (int ni = 0; ni < 2; ++ni) {
+                    const int jj = wc * 64 + ni * 32 + l32;
+                    const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
 #pragma unroll
-                for (int rg = 0; rg < 4; ++rg) {
-                    const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+                    for (int rg = 0; rg < 4; ++rg) {
+                        const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        float b = acc[mi][ni][4 * rg + r];
-                        if (e.scale) b *= rs[ii0 + r] * s_j;
-                        float v = kappa_from_dot(b, rn[ii0 + r], nrm_j, e.kernel, e.gamma,
-                                                 e.coef0, e.degree);
-                        if (diag_tile && ii0 + r == jj) {
-                            // kappa(x, x) = exp(0) = 1 exactly; a non-finite row stays visible
-                            v = (e.kernel == KKM_GAUSS) ? (isfinite(b) ? 1.0f : __builtin_nanf(""))
-                                                        : Store<OUT>::round(v);
-                            if (m0 + jj < e.n) e.diag[m0 + jj] = v;
+                        for (int r = 0; r < 4; ++r) {
+                            float b = acc[mi][ni][4 * rg + r];
+                            if (e.scale) b *= rs[ii0 + r] * s_j;
+                            float v = kappa_from_dot(b, rn[ii0 + r], nrm_j, e.kernel, e.gamma,
+                                                     e.coef0, e.degree);
+                            if (diag_tile && ii0 + r == jj) {
+                                // kappa(x, x) = exp(0) = 1 exactly; a non-finite row stays visible
+                                v = (e.kernel == KKM_GAUSS) ? (isfinite(b) ? 1.0f : __builtin_nanf(""))
+                                                            : Store<OUT>::round(v);
+                                if (m0 + jj < e.n) e.diag[m0 + jj] = v;
+                            }
+                            T[(ii0 + r) * TS + jj] = v;
                         }
-                        T[(ii0 + r) * TS + jj] = v;
                     }
                 }
-            }
-        __syncthreads();
-        store_rows<OUT>(e, T, m0, n0);  // rows and columns may pass n
-        __syncthreads();
-        return;
-    }
-    if (!diag_tile) {
+            __syncthreads();
+            store_rows<OUT>(e, T, m0, n0);  // rows and columns may pass n
+            __syncthreads();
+            return;
+        }
+        if (!diag_tile) {
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+            for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni) {
-                const int jj = wc * 64 + ni * 32 + l32;
-                const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
+                for (int ni = 0; ni < 2; ++ni) {
+                    const int jj = wc * 64 + ni * 32 + l32;
+                    const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
 #pragma unroll
-                for (int rg = 0; rg < 4; ++rg) {
-                    const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+                    for (int rg = 0; rg < 4; ++rg) {
+                        const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        float b = acc[mi][ni][4 * rg + r];
-                        if (e.scale) b *= rs[ii0 + r] * s_j;
-                        acc[mi][ni][4 * rg + r] = kappa_from_dot(b, rn[ii0 + r], nrm_j, e.kernel,
-                                                                 e.gamma, e.coef0, e.degree);
+                        for (int r = 0; r < 4; ++r) {
+                            float b = acc[mi][ni][4 * rg + r];
+                            if (e.scale) b *= rs[ii0 + r] * s_j;
+                            acc[mi][ni][4 * rg + r] = kappa_from_dot(b, rn[ii0 + r], nrm_j, e.kernel,
+                                                                     e.gamma, e.coef0, e.degree);
+                        }
+                        // transposed: T[jj][ii0 .. ii0+3]
+                        const f32x4 w = {acc[mi][ni][4 * rg], acc[mi][ni][4 * rg + 1],
+                                         acc[mi][ni][4 * rg + 2], acc[mi][ni][4 * rg + 3]};
+                        *reinterpret_cast<f32x4 *>(T + jj * TS + ii0) = w;
                     }
-                    // transposed: T[jj][ii0 .. ii0+3]
-                    const f32x4 w = {acc[mi][ni][4 * rg], acc[mi][ni][4 * rg + 1],
-                                     acc[mi][ni][4 * rg + 2], acc[mi][ni][4 * rg + 3]};
-                    *reinterpret_cast<f32x4 *>(T + jj * TS + ii0) = w;
                 }
-            }
-        __syncthreads();
-        store_rows<OUT>(e, T, n0, m0);  // K[n0 + jj][m0 ..]; off the diagonal m0 + 127 < n0
-        __syncthreads();
-        // as is: T[ii][jj]
+            __syncthreads();
+            store_rows<OUT>(e, T, n0, m0);  // K[n0 + jj][m0 ..]; off the diagonal m0 + 127 < n0
+            __syncthreads();
+            // as is: T[ii][jj]
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+            for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni) {
-                const int jj = wc * 64 + ni * 32 + l32;
+                for (int ni = 0; ni < 2; ++ni) {
+                    const int jj = wc * 64 + ni * 32 + l32;
 #pragma unroll
-                for (int rg = 0; rg < 4; ++rg) {
-                    const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+                    for (int rg = 0; rg < 4; ++rg) {
+                        const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) T[(ii0 + r) * TS + jj] = acc[mi][ni][4 * rg + r];
+                        for (int r = 0; r < 4; ++r) T[(ii0 + r) * TS + jj] = acc[mi][ni][4 * rg + r];
+                    }
                 }
+            __syncthreads();
+            store_rows<OUT>(e, T, m0, n0);  // K[m0 + ii][n0 ..]: every row exists; columns may pass n
+            __syncthreads();
+            return;
+        }
+    } else {
+        if constexpr (FULL) {
+            // as is, RH rows at a time (in halves: the waves with wr == h hold them)
+#pragma unroll
+            for (int h = 0; h < HALVES; ++h) {
+                if (HALVES == 1 || wr == h) {
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni) {
+                            const int jj = wc * 64 + ni * 32 + l32;
+                            const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
+#pragma unroll
+                            for (int rg = 0; rg < 4; ++rg) {
+                                const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    float b = acc[mi][ni][4 * rg + r];
+                                    if (e.scale) b *= rs[ii0 + r] * s_j;
+                                    float v = kappa_from_dot(b, rn[ii0 + r], nrm_j, e.kernel, e.gamma,
+                                                             e.coef0, e.degree);
+                                    if (diag_tile && ii0 + r == jj) {
+                                        // kappa(x, x) = exp(0) = 1 exactly; a non-finite row stays visible
+                                        v = (e.kernel == KKM_GAUSS)
+                                                ? (isfinite(b) ? 1.0f : __builtin_nanf(""))
+                                                : Store<OUT>::round(v);
+                                        if (m0 + jj < e.n) e.diag[m0 + jj] = v;
+                                    }
+                                    T[(ii0 - RH * h + r) * TS + jj] = v;
+                                }
+                            }
+                        }
+                }
+                __syncthreads();
+                store_rows<OUT, RH>(e, T, m0 + RH * h, n0);  // rows and columns may pass n
+                __syncthreads();
             }
-        __syncthreads();
-        store_rows<OUT>(e, T, m0, n0);  // K[m0 + ii][n0 ..]: every row exists; columns may pass n
-        __syncthreads();
-        return;
+            return;
+        }
+        if (!diag_tile) {
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni) {
+                    const int jj = wc * 64 + ni * 32 + l32;
+                    const float nrm_j = rn[GM + jj], s_j = rs[GM + jj];
+#pragma unroll
+                    for (int rg = 0; rg < 4; ++rg) {
+                        const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            float b = acc[mi][ni][4 * rg + r];
+                            if (e.scale) b *= rs[ii0 + r] * s_j;
+                            acc[mi][ni][4 * rg + r] = kappa_from_dot(b, rn[ii0 + r], nrm_j, e.kernel,
+                                                                     e.gamma, e.coef0, e.degree);
+                        }
+                    }
+                }
+            // transposed, RH columns at a time (in halves: the waves with wc == h
+            // hold them): T[jj - RH h][ii], then rows K[n0 + jj][m0 ..]; off the
+            // diagonal m0 + 127 < n0
+#pragma unroll
+            for (int h = 0; h < HALVES; ++h) {
+                if (HALVES == 1 || wc == h) {
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni) {
+                            const int jl = wc * 64 + ni * 32 + l32 - RH * h;
+#pragma unroll
+                            for (int rg = 0; rg < 4; ++rg) {
+                                const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+                                const f32x4 w = {acc[mi][ni][4 * rg], acc[mi][ni][4 * rg + 1],
+                                                 acc[mi][ni][4 * rg + 2], acc[mi][ni][4 * rg + 3]};
+                                *reinterpret_cast<f32x4 *>(T + jl * TS + ii0) = w;
+                            }
+                        }
+                }
+                __syncthreads();
+                store_rows<OUT, RH>(e, T, n0 + RH * h, m0);
+                __syncthreads();
+            }
+            // as is, RH rows at a time: every row exists; columns may pass n
+#pragma unroll
+            for (int h = 0; h < HALVES; ++h) {
+                if (HALVES == 1 || wr == h) {
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni) {
+                            const int jj = wc * 64 + ni * 32 + l32;
+#pragma unroll
+                            for (int rg = 0; rg < 4; ++rg) {
+                                const int il0 = wr * 64 + mi * 32 + 8 * rg + 4 * half - RH * h;
+#pragma unroll
+                                for (int r = 0; r < 4; ++r)
+                                    T[(il0 + r) * TS + jj] = acc[mi][ni][4 * rg + r];
+                            }
+                        }
+                }
+                __syncthreads();
+                store_rows<OUT, RH>(e, T, m0 + RH * h, n0);
+                __syncthreads();
+            }
+            return;
+        }
     }
     // diagonal tile: the upper triangle is the source of truth
 #pragma unroll
@@ -490,7 +601,7 @@ __device__ __forceinline__ void f32_tile(const F32Tile &a, int64_t bi, int64_t b
         if (kt + 1 < nk) sstore(buf ^ 1);
         __syncthreads();
     }
-    static_assert(sizeof(lds.op) >= EPI_LDS_BYTES, "epilogue tile does not fit");
+    static_assert(sizeof(lds.op) >= epi_lds_bytes(1), "epilogue tile does not fit");
     epilogue<OUT, FULL>(a.e, acc, m0, n0, bi == bj, wr, wc, lane, &lds.op[0][0][0], lds.rn, lds.rs);
 }
 
@@ -517,8 +628,13 @@ struct LowpTile {
     Epi e;
 };
 
+// DB: two sets of slabs (one barrier per slab; the epilogue stages the whole
+// tile); else one set (the next slab waits in registers, two barriers per
+// slab, the epilogue stages half a tile at a time): about half the LDS, so
+// three workgroups fit on a CU.
+template <bool DB>
 struct LowpLds {
-    unsigned char op[2][2][GM * SLD];  // operand slabs, double-buffered
+    unsigned char op[DB ? 2 : 1][2][GM * SLD];
     float rn[2 * GM], rs[2 * GM];
 };
 
@@ -530,8 +646,8 @@ inline int64_t padded_d(int64_t d, int32_t gram_prec) {
 
 // One 128 x 128 tile (bi, bj) of the product and its epilogue, by the 256
 // threads of a workgroup, staging through `lds`.
-template <int PREC, typename OUT, bool FULL = false>
-__device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t bj, LowpLds &lds) {
+template <int PREC, typename OUT, bool FULL = false, bool DB = true>
+__device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t bj, LowpLds<DB> &lds) {
     const int64_t m0 = bi * GM, n0 = bj * GM;
 
     const int tid = threadIdx.x;
@@ -582,7 +698,7 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
     const int half = lane >> 5;
     const int l32 = lane & 31;
     for (int64_t kt = 0; kt < a.nslab; ++kt) {
-        const int buf = kt & 1;
+        const int buf = DB ? (int)(kt & 1) : 0;
         if (kt + 1 < a.nslab) gload(kt + 1);
         const unsigned char *As = lds.op[buf][0];
         const unsigned char *Bs = lds.op[buf][1];
@@ -625,12 +741,20 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
                         acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(x, y, acc[mi][ni], 0, 0, 0);
                     }
         }
-        if (kt + 1 < a.nslab) sstore(buf ^ 1);
-        __syncthreads();
+        if constexpr (DB) {
+            if (kt + 1 < a.nslab) sstore(buf ^ 1);
+            __syncthreads();
+        } else {
+            __syncthreads();  // every read of the slab is done
+            if (kt + 1 < a.nslab) {
+                sstore(0);
+                __syncthreads();
+            }
+        }
     }
-    static_assert(sizeof(lds.op) >= EPI_LDS_BYTES, "epilogue tile does not fit");
-    epilogue<OUT, FULL>(a.e, acc, m0, n0, bi == bj, wr, wc, lane,
-                        reinterpret_cast<float *>(&lds.op[0][0][0]), lds.rn, lds.rs);
+    static_assert(sizeof(lds.op) >= epi_lds_bytes(DB ? 1 : 2), "epilogue tile does not fit");
+    epilogue<OUT, FULL, DB ? 1 : 2>(a.e, acc, m0, n0, bi == bj, wr, wc, lane,
+                                    reinterpret_cast<float *>(&lds.op[0][0][0]), lds.rn, lds.rs);
 }
 
 // ---------------------------------------------------------------- BF16 / FP8 product, 256 x 256 tiles
@@ -763,7 +887,7 @@ __device__ __forceinline__ void lowp_tile256(const LowpTile &a, int64_t bi, int6
         if (kt + 1 < a.nslab) sstore(buf ^ 1);
         __syncthreads();
     }
-    static_assert(sizeof(lds.op) >= EPI_LDS_BYTES, "epilogue tile does not fit");
+    static_assert(sizeof(lds.op) >= epi_lds_bytes(1), "epilogue tile does not fit");
     float *T = reinterpret_cast<float *>(&lds.op[0][0][0]);
     // the quadrants one by one, with compile-time indices into acc (a loop
     // too large to unroll would index it at run time and force it into memory)
