@@ -58,7 +58,7 @@ TRAFFIC = {
 # feature network and its training (learned warm start)
 H1, H2, OUT = 512, 512, 256
 TRAIN_BATCH, TRAIN_STEPS, TRAIN_LR = 64, 2442, 1e-3  # 2442 * 64^2 = 1.0e7 kernel values
-WARM_RESTARTS, WARM_MAX_ITER = 4, 60
+WARM_RESTARTS, WARM_MAX_ITER = 8, 60
 
 
 def sources_sha(paths):

@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void gemm_wide(GemmArgs g, int epi, int vec
 }  // namespace
 
 bool gemm_wide_fits(bool ak, bool bk, GemmEpi epi, const GemmArgs &g) {
-    return ak && bk && epi != EPI_LOSS && g.M >= 64 && g.N >= 256 && g.M * g.N >= (1 << 20);
+    return ak && bk && epi != EPI_LOSS && g.M >= 32 && g.N >= 256 && g.M * g.N >= (1 << 20);
 }
 
 kkm_status gemm_launch(GemmOp op, bool ak, bool bk, GemmEpi epi, const GemmArgs &g,

@@ -121,30 +121,57 @@ __global__ __launch_bounds__(256) void centroid_partials(const float *F, int64_t
     }
 }
 
-// one workgroup per cluster: centroid = sum of its chunk partials / |c|, and ||c||^2
+// One workgroup per cluster: centroid = sum of its chunk partials / |c|, and
+// ||c||^2.  Thread t takes features 4 (t % 64) .. + 3 of each 256-feature
+// block and chunks t / 64, t / 64 + 4, ...; the four chunk lanes are then
+// added pairwise in a fixed order.
 __global__ __launch_bounds__(256) void centroid_finalize(const float *Cp, int64_t f, int32_t k,
                                                          const int32_t *offsets, float *C,
                                                          float *cn) {
+    __shared__ f32x4 part[4][64];
     __shared__ float sh[256];
     const int c = blockIdx.x;
+    const int tid = threadIdx.x, fq = tid & 63, cl = tid >> 6;
     const int64_t a = offsets[c], b = offsets[c + 1];
+    const int64_t q0 = (b > a) ? a / kRows : 0, q1 = (b > a) ? (b - 1) / kRows : -1;
+    const bool vec = (f & 3) == 0 && (reinterpret_cast<uintptr_t>(Cp) & 15) == 0;
     float sq = 0.f;
-    for (int64_t t = threadIdx.x; t < f; t += 256) {
-        float s = 0.f;
-        if (b > a) {
-            for (int64_t q = a / kRows; q <= (b - 1) / kRows; ++q) s += Cp[(q + c) * f + t];
-            s /= (float)(b - a);
+    for (int64_t f0 = 0; f0 < f; f0 += 256) {
+        const int64_t t0 = f0 + 4 * fq;
+        f32x4 s = {0.f, 0.f, 0.f, 0.f};
+        for (int64_t q = q0 + cl; q <= q1; q += 4) {
+            const float *src = Cp + (q + c) * f + t0;
+            if (vec && t0 + 3 < f) {
+                const f32x4 v = *reinterpret_cast<const f32x4 *>(src);
+                s += v;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (t0 + u < f) s[u] += src[u];
+            }
         }
-        C[(int64_t)c * f + t] = s;
-        sq = fmaf(s, s, sq);
-    }
-    sh[threadIdx.x] = sq;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        part[cl][fq] = s;
+        __syncthreads();
+        if (cl == 0) {
+            const f32x4 tot = (part[0][fq] + part[1][fq]) + (part[2][fq] + part[3][fq]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (t0 + u >= f) break;
+                // sum / |c| (an empty cluster keeps a zero centroid)
+                const float v = (b > a) ? tot[u] / (float)(b - a) : 0.f;
+                C[(int64_t)c * f + t0 + u] = v;
+                sq = fmaf(v, v, sq);
+            }
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) cn[c] = sh[0];
+    sh[tid] = sq;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) sh[tid] += sh[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) cn[c] = sh[0];
 }
 
 // Gt = C F^T ([k][n]: consecutive threads read consecutive entries).
