@@ -47,11 +47,11 @@ BF16_MFMA_PEAK_TFS = 2500.0
 TRAFFIC = {
     "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
                        "sha256": "5dfa764ff32bcad8404bb7b0d925b865fc7dfd0af7fedd260eee0ae69eda4208",
-                       "n": 200000, "fetch_kib": 78169238.1, "write_kib": 85551.3,
+                       "n": 200000, "fetch_kib": 78169660.7, "write_kib": 85552.3,
                        "fetch_scale": 1.9999, "write_scale": 1.0},
     "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_tile.h", "csrc/kkm_common.h"],
-                      "sha256": "0495d6dbc5eeb0508091ec838cdce9b1620d2ad1c5defc5c5c899e81f2f85226",
-                      "n": 200000, "fetch_kib": 162599214.9, "write_kib": 156250891.9,
+                      "sha256": "5a13ae2cbd120acd615ce965558fa89caa04c4de88b4abeabf312f2a490ba1f7",
+                      "n": 200000, "fetch_kib": 160830564.2, "write_kib": 156250900.2,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }
 
