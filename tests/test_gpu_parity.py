@@ -257,3 +257,19 @@ def test_256_tile_equals_128_tile(kkm, gp, ks, n, d):
         torch.cuda.synchronize()
         assert torch.equal(a, b), (gp, ks, kern, (a != b).sum().item())
         assert torch.equal(da, db)
+
+
+def test_gram_shape_values(kkm):
+    """An FP32 product ignores the tile-size request (always 128 x 128: same K
+    bit for bit); an unknown shape is rejected before any work."""
+    import torch
+    X = np.random.default_rng(3).normal(0, 1, (300, 40)).astype(np.float32)
+    Xd = to_dev(X)
+    a, da = kkm.kkm_gram(Xd, kkm.GAUSS, 0.05)
+    for shape in (kkm.GRAM_TRIANGLE_128, kkm.GRAM_TRIANGLE_256):
+        b, db = kkm.kkm_gram(Xd, kkm.GAUSS, 0.05, shape=shape)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b) and torch.equal(da, db), shape
+    with pytest.raises(kkm.KKMError) as e:
+        kkm.kkm_gram(Xd, kkm.GAUSS, 0.05, shape=7)
+    assert e.value.status == -1
