@@ -59,6 +59,7 @@ TRAFFIC = {
 H1, H2, OUT = 512, 512, 256
 TRAIN_BATCH, TRAIN_STEPS, TRAIN_LR = 64, 2442, 1e-3  # 2442 * 64^2 = 1.0e7 kernel values
 WARM_RESTARTS, WARM_MAX_ITER = 8, 60
+WARM_STREAMS = 4  # restarts run concurrently on this many streams
 
 
 def sources_sha(paths):
@@ -159,21 +160,53 @@ def train_feature_map(kkm, torch, w, dev):
     return params, rep
 
 
-def warm_labels(kkm, w, params, Xd, seed):
+def warm_labels(kkm, w, params, Xd, seed, streams=WARM_STREAMS):
     """phi_theta(X), then WARM_RESTARTS k-means++ seedings each followed by
     Lloyd in feature space; keeps the labelling with the lowest feature-space
-    objective.  Returns (labels, cheap iterations summed over restarts)."""
+    objective (the lowest restart index on ties).  Returns (labels, cheap
+    iterations summed over restarts).  The restarts are independent; they run
+    on `streams` HIP streams of default priority, one host thread each (the
+    library calls release the interpreter lock), and each restart computes
+    exactly what it computes alone."""
+    import threading
+
+    import torch
+
     import datagen
     F = kkm.kkm_mlp_forward(params, Xd, H1, H2, OUT)
-    best, cheap = None, 0
-    for r in range(WARM_RESTARTS):
-        _, seeded = kkm.kkm_feature_kmeanspp(F, w.k, datagen.uniforms(w.k, seed + r))
-        lab, it, _, obj = kkm.kkm_feature_lloyd(F, w.k, seeded, max_iter=WARM_MAX_ITER,
-                                                return_objective=True)
-        cheap += it
-        if best is None or obj < best[0]:
-            best = (obj, lab)
-    return best[1], cheap
+    main = torch.cuda.current_stream()
+    ready = torch.cuda.Event()
+    ready.record(main)
+    out = [None] * WARM_RESTARTS
+    side = [torch.cuda.Stream() for _ in range(max(1, streams))]
+    errors = []
+
+    def worker(t):
+        try:
+            st = side[t]
+            with torch.cuda.stream(st):
+                st.wait_event(ready)
+                for r in range(t, WARM_RESTARTS, len(side)):
+                    _, seeded = kkm.kkm_feature_kmeanspp(F, w.k, datagen.uniforms(w.k, seed + r))
+                    lab, it, _, obj = kkm.kkm_feature_lloyd(F, w.k, seeded, max_iter=WARM_MAX_ITER,
+                                                            return_objective=True)
+                    out[r] = (obj, it, lab)
+        except Exception as e:  # re-raised on the calling thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(len(side))]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    if errors:
+        raise errors[0]
+    for st in side:
+        main.wait_stream(st)
+    best = min(range(WARM_RESTARTS), key=lambda r: (out[r][0], r))
+    lab = out[best][2]
+    lab.record_stream(main)
+    return lab, sum(o[1] for o in out)
 
 
 def learned_c5_leg(kkm, torch, dev):
