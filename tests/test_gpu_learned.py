@@ -264,3 +264,45 @@ def test_learned_warm_start_gain(kkm):
     # the gain: a better local optimum of the same objective (exact iterations
     # are reported; on the full-size workload the benchmark shows the time saved)
     assert learned["objective"] < plain["objective"] * (1 - 1e-3)
+
+
+def test_concurrent_streams_match_sequential(kkm):
+    """The library holds no shared mutable state between calls: k-means++
+    seedings and feature-space Lloyd runs issued from four host threads on
+    four streams give exactly the labels of the same calls made one after
+    another."""
+    import threading
+
+    import torch
+    rng = np.random.default_rng(21)
+    n, f, k = 6000, 64, 24
+    mu = rng.normal(0, 2, (k, f))
+    F = to_dev((mu[rng.integers(0, k, n)] + rng.normal(0, 1, (n, f))).astype(np.float32))
+    us = [datagen.uniforms(k, 900 + r) for r in range(8)]
+
+    def run(r):
+        _, seeded = kkm.kkm_feature_kmeanspp(F, k, us[r])
+        lab, it, _, obj = kkm.kkm_feature_lloyd(F, k, seeded, max_iter=50, return_objective=True)
+        return lab, it, obj
+
+    seq = [run(r) for r in range(8)]
+    torch.cuda.synchronize()
+    out = [None] * 8
+    main = torch.cuda.current_stream()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+
+    def worker(t):
+        with torch.cuda.stream(streams[t]):
+            streams[t].wait_stream(main)
+            for r in range(t, 8, 4):
+                out[r] = run(r)
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    for r in range(8):
+        assert torch.equal(seq[r][0], out[r][0]), r
+        assert seq[r][1] == out[r][1] and seq[r][2] == out[r][2], r
