@@ -50,7 +50,7 @@ TRAFFIC = {
                        "n": 200000, "fetch_kib": 78169660.7, "write_kib": 85552.3,
                        "fetch_scale": 1.9999, "write_scale": 1.0},
     "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_tile.h", "csrc/kkm_common.h"],
-                      "sha256": "5a13ae2cbd120acd615ce965558fa89caa04c4de88b4abeabf312f2a490ba1f7",
+                      "sha256": "50f85bd9f32aa068be140202f556027e826462f5f6b4933083f3e8d392393e86",
                       "n": 200000, "fetch_kib": 160830564.2, "write_kib": 156250900.2,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }

@@ -20,7 +20,8 @@
 //         E4M3 (round to nearest even, clamped to +-448), FP32 accumulation,
 //         v_mfma_f32_32x32x16_fp8_fp8; B_ij = s_i s_j sum_l q_il q_jl.
 // For BF16/FP8 the squared norms of the Gaussian are taken from the same
-// rounded values.  K is stored as FP32 or bfloat16 (k_store).
+// rounded values.  K is stored as FP32 or bfloat16 (k_store).  The Gaussian is
+// evaluated as 2^(-gamma log2(e) s) with the hardware base-2 exponential.
 #include "gram_tile.h"
 
 namespace kkm {

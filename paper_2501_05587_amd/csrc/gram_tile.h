@@ -1,8 +1,9 @@
 // Device-side pieces of the kernel-matrix product shared by the single- and
 // many-instance Gram kernels: the 128 x 128 tile of the FP32 and of the
 // BF16 / FP8 MFMA product with its fused epilogue (kappa, diagonal, mirrored
-// stores), and the row prologues (squared norm; rounding to the product's
-// input type).  Internal to the library.
+// stores), the 256 x 256 BF16 / FP8 tile (selectable, not the default), the
+// launch order of the tiles, and the row prologues (squared norm; rounding to
+// the product's input type).  Internal to the library.
 #pragma once
 
 #include <type_traits>
@@ -144,10 +145,12 @@ __device__ __forceinline__ void stage_norms(const Epi &e, int64_t m0, int64_t n0
 //
 // Off the diagonal kappa replaces the accumulators in place, then the tile
 // goes through `T` twice, transposed for K[j][i] and as is for K[i][j], so
-// that both leave as whole rows of 4-element vector stores.  `T`
-// (EPI_LDS_BYTES) may alias the operand buffers: the caller's last barrier
-// has retired every read of them.  The trailing barrier retires every read of
-// `T`, `rn` and `rs` before the workgroup's next tile.
+// that both leave as whole rows of 4-element vector stores; HALVES = 2 stages
+// half of the tile at a time (64 columns of the transposed pass, 64 rows of
+// the other, by the two waves that hold them).  `T` (epi_lds_bytes(HALVES))
+// may alias the operand buffers: the caller's last barrier has retired every
+// read of them.  The trailing barrier retires every read of `T`, `rn` and `rs`
+// before the workgroup's next tile.
 //
 // FULL (every tile of the square is launched, the GEMM shape of the product):
 // each tile writes only its own block K[i][j], through `T` as is; a diagonal
