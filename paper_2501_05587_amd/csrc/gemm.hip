@@ -289,11 +289,13 @@ __global__ __launch_bounds__(256, 2) void gemm_wide(GemmArgs g, int epi, int vec
     }
 }
 
-}  // namespace
-
+// Products that take the wide tiles: both operands k-contiguous, no loss
+// epilogue (its per-workgroup sums are laid out for 64 x 64 tiles), and large.
 bool gemm_wide_fits(bool ak, bool bk, GemmEpi epi, const GemmArgs &g) {
     return ak && bk && epi != EPI_LOSS && g.M >= 32 && g.N >= 256 && g.M * g.N >= (1 << 20);
 }
+
+}  // namespace
 
 kkm_status gemm_launch(GemmOp op, bool ak, bool bk, GemmEpi epi, const GemmArgs &g,
                        hipStream_t stream) {
