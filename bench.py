@@ -214,7 +214,7 @@ def learned_c5_leg(kkm, torch, dev):
     kernel values of the 32-component mixture in R^128, then fresh n=100000
     draws, k=32: plain FP32 from random labels against the BF16 form from the
     learned warm start, both to convergence, and the FP32 form converged from
-    the same warm labels as the judge of the result (ARI)."""
+    the same warm labels as the reference for the result (ARI)."""
     import numpy as np
 
     import datagen
@@ -430,7 +430,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -51,7 +51,7 @@ typedef enum {
     KKM_ERR_LABEL = -2,       /* an input label lies outside [0, k)             */
     KKM_ERR_NOMEM = -3,       /* a device allocation or a workspace is too small */
     KKM_ERR_HIP = -4,         /* the HIP runtime reported an error               */
-    KKM_ERR_UNSUPPORTED = -5, /* valid request this build does not implement    */
+    KKM_ERR_UNSUPPORTED = -5, /* valid request the library does not implement   */
     KKM_ERR_NONFINITE = -6    /* the kernel matrix has a non-finite diagonal     */
 } kkm_status;
 
