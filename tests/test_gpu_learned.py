@@ -197,7 +197,10 @@ def test_feature_lloyd_converges_and_rejects_bad_labels(kkm):
         kkm.kkm_feature_lloyd(to_dev(F), 6, to_dev(bad), max_iter=3)
 
 
-@pytest.mark.parametrize("n,f,k", [(2000, 256, 16), (333, 7, 9), (40, 3, 40), (8000, 66, 200)])
+# (70000, 16, 12): more than 256 row groups, so each thread of the seed
+# selection sums two group totals before the block scan
+@pytest.mark.parametrize("n,f,k", [(2000, 256, 16), (333, 7, 9), (40, 3, 40), (8000, 66, 200),
+                                   (70000, 16, 12)])
 def test_feature_kmeanspp_parity(kkm, n, f, k):
     import torch
     rng = np.random.default_rng(n + k)
