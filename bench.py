@@ -49,7 +49,7 @@ TRAFFIC = {
                        "sha256": "5dfa764ff32bcad8404bb7b0d925b865fc7dfd0af7fedd260eee0ae69eda4208",
                        "n": 200000, "fetch_kib": 78169660.7, "write_kib": 85552.3,
                        "fetch_scale": 1.9999, "write_scale": 1.0},
-    "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_tile.h", "csrc/kkm_common.h"],
+    "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_f32.hip", "csrc/gram_tile.h", "csrc/kkm_common.h"],
                       "sha256": "50f85bd9f32aa068be140202f556027e826462f5f6b4933083f3e8d392393e86",
                       "n": 200000, "fetch_kib": 160830564.2, "write_kib": 156250900.2,
                       "fetch_scale": 1.9999, "write_scale": 1.0},

@@ -23,8 +23,33 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+def _includes(path, seen):
+    """Every header `path` includes with #include "...", transitively."""
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("#include \""):
+                h = os.path.normpath(os.path.join(os.path.dirname(path), line.split('"')[1]))
+                if h not in seen and os.path.exists(h):
+                    seen.add(h)
+                    _includes(h, seen)
+    return seen
+
+
+def _object(src):
+    return os.path.join(BUILD, os.path.basename(src) + ".o")
+
+
+def _stale(src):
+    obj = _object(src)
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(t < os.path.getmtime(p) for p in [src, *_includes(src, set())])
+
+
 def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    obj = _object(src)
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -34,15 +59,22 @@ def _compile(src):
     return obj, warn
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source and link libkkm.so; returns its path."""
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every HIP source and link libkkm.so; returns its path.  With
+    incremental=True only sources whose object is older than the source or any
+    header are compiled again."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(_compile, srcs))
-    objs = [o for o, _ in results]
+    todo = srcs
+    if incremental:
+        todo = [s for s in srcs if _stale(s)]
+    results = []
+    if todo:
+        with cf.ThreadPoolExecutor(max_workers=min(8, len(todo))) as ex:
+            results = list(ex.map(_compile, todo))
+    objs = [_object(s) for s in srcs]
     if verbose:
-        for (_, w), s in zip(results, srcs):
+        for (_, w), s in zip(results, todo):
             if w:
                 print("[%s]\n%s" % (os.path.basename(s), w), file=sys.stderr)
     tmp = LIB + ".tmp%d" % os.getpid()
@@ -55,4 +87,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

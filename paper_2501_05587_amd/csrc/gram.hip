@@ -30,35 +30,6 @@ namespace {
 
 using namespace gt;
 
-// ---------------------------------------------------------------- FP32 product
-
-template <typename OUT, bool FULL>
-__global__ __launch_bounds__(GTHREADS, 2) void gram_f32_mfma(F32Tile a, TileOrder o) {
-    __shared__ __attribute__((aligned(16))) F32Lds lds;
-    int64_t bi, bj;
-    if (!tile_of_block(o, bi, bj)) return;
-    f32_tile<OUT, FULL>(a, bi, bj, lds);
-}
-
-// ---------------------------------------------------------------- BF16 / FP8 product
-
-// One tile per workgroup, three workgroups per CU (single-buffered slabs).
-template <int PREC, typename OUT, bool FULL>
-__global__ __launch_bounds__(GTHREADS, 3) void gram_lowp_mfma(LowpTile a, TileOrder o) {
-    __shared__ __attribute__((aligned(16))) LowpLds<false> lds;
-    int64_t bi, bj;
-    if (!tile_of_block(o, bi, bj)) return;
-    lowp_tile<PREC, OUT, FULL, false>(a, bi, bj, lds);
-}
-
-template <int PREC, typename OUT>
-__global__ __launch_bounds__(GTHREADS, 1) void gram_lowp_mfma256(LowpTile a, TileOrder o) {
-    __shared__ __attribute__((aligned(16))) LowpLds256 lds;
-    int64_t bi, bj;
-    if (!tile_of_block(o, bi, bj)) return;
-    lowp_tile256<PREC, OUT>(a, bi, bj, lds);
-}
-
 // ---------------------------------------------------------------- prologues
 
 // Squared row norms ||x_i||^2 for the Gaussian (FP32 product): one wave per row.
@@ -81,34 +52,6 @@ __global__ __launch_bounds__(256) void quantize_rows(const float *X, int64_t n, 
     const int64_t eb = (PREC == KKM_BF16) ? 2 : 1;
     quantize_row<PREC>(X + row * ldx, d, dpad, Xq + row * dpad * eb, nrm + row, scale + row,
                        threadIdx.x & 63);
-}
-
-void lowp256_dispatch(int32_t gram_prec, int32_t k_store, dim3 g, dim3 b, const LowpTile &a,
-                      const TileOrder &order, hipStream_t stream) {
-    if (gram_prec == KKM_BF16 && k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma256<KKM_BF16, float>), g, b, 0, stream, a, order);
-    else if (gram_prec == KKM_BF16)
-        hipLaunchKernelGGL((gram_lowp_mfma256<KKM_BF16, uint16_t>), g, b, 0, stream, a, order);
-    else if (k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma256<KKM_FP8_ROWSCALED, float>), g, b, 0, stream, a, order);
-    else
-        hipLaunchKernelGGL((gram_lowp_mfma256<KKM_FP8_ROWSCALED, uint16_t>), g, b, 0, stream, a,
-                           order);
-}
-
-template <bool FULL>
-void lowp_dispatch(int32_t gram_prec, int32_t k_store, dim3 g, dim3 b, const LowpTile &a,
-                   const TileOrder &order, hipStream_t stream) {
-    if (gram_prec == KKM_BF16 && k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, float, FULL>), g, b, 0, stream, a, order);
-    else if (gram_prec == KKM_BF16)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_BF16, uint16_t, FULL>), g, b, 0, stream, a, order);
-    else if (k_store == KKM_F32)
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, float, FULL>), g, b, 0, stream, a,
-                           order);
-    else
-        hipLaunchKernelGGL((gram_lowp_mfma<KKM_FP8_ROWSCALED, uint16_t, FULL>), g, b, 0, stream,
-                           a, order);
 }
 
 // log2 of the tile group edge of the launch order: 8 x 8 groups, so the 64
@@ -182,15 +125,7 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
         a.vec_x = ((ldx % 4) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
         a.e = e;
         const TimedSpan span = timing_begin(TK_GRAM, stream);
-        const dim3 g((unsigned)grid), b(GTHREADS);
-        if (k_store == KKM_F32 && !full)
-            hipLaunchKernelGGL((gram_f32_mfma<float, false>), g, b, 0, stream, a, order);
-        else if (k_store == KKM_F32)
-            hipLaunchKernelGGL((gram_f32_mfma<float, true>), g, b, 0, stream, a, order);
-        else if (!full)
-            hipLaunchKernelGGL((gram_f32_mfma<uint16_t, false>), g, b, 0, stream, a, order);
-        else
-            hipLaunchKernelGGL((gram_f32_mfma<uint16_t, true>), g, b, 0, stream, a, order);
+        launch_gram_f32(k_store, full, dim3((unsigned)grid), a, order, stream);
         KKM_HIP(hipGetLastError());
         timing_end(span, stream);
         return KKM_OK;
@@ -214,13 +149,10 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
     a.e = e;
     if (gram_prec == KKM_FP8_ROWSCALED) a.e.scale = scale;
     const TimedSpan span = timing_begin(TK_GRAM, stream);
-    const dim3 g((unsigned)grid), b(GTHREADS);
     if (big)
-        lowp256_dispatch(gram_prec, k_store, g, b, a, order, stream);
-    else if (!full)
-        lowp_dispatch<false>(gram_prec, k_store, g, b, a, order, stream);
+        launch_gram_lowp256(gram_prec, k_store, dim3((unsigned)grid), a, order, stream);
     else
-        lowp_dispatch<true>(gram_prec, k_store, g, b, a, order, stream);
+        launch_gram_lowp(gram_prec, k_store, full, dim3((unsigned)grid), a, order, stream);
     KKM_HIP(hipGetLastError());
     timing_end(span, stream);
     return KKM_OK;

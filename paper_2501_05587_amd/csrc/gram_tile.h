@@ -975,6 +975,14 @@ __device__ __forceinline__ void quantize_row(const float *x, int64_t d, int64_t 
     if (lane == 0) *nrm = (PREC == KKM_FP8_ROWSCALED) ? s * s * acc : acc;
 }
 
+// Launchers of the product kernels, one translation unit each (gram_f32.hip,
+// gram_lowp.hip, gram_lowp256.hip); g is the grid of the launch order.
+void launch_gram_f32(int32_t k_store, bool full, dim3 g, const F32Tile &a, const TileOrder &order,
+                     hipStream_t stream);
+void launch_gram_lowp(int32_t gram_prec, int32_t k_store, bool full, dim3 g, const LowpTile &a,
+                      const TileOrder &order, hipStream_t stream);
+void launch_gram_lowp256(int32_t gram_prec, int32_t k_store, dim3 g, const LowpTile &a,
+                         const TileOrder &order, hipStream_t stream);
 
 }  // namespace gt
 }  // namespace kkm
