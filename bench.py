@@ -4,26 +4,39 @@
 Workload: a 64-component Gaussian mixture in R^1024 (means N(0,1), sigma 0.5),
 Gaussian kernel gamma = 1/1024, random initial labels.
 
-Plain FP32 leg (the timed steps behind `value`).  One step = one complete run
-of the method on the resident input: the Gram kernel K = kappa(X X^T) (FP32
-MFMA, K stored FP32, 160 GB) followed by 30 reassignment steps (V in CSR form,
-SpMM row sweep of K, centroid norms, fused distance/argmin/histogram) and the
-FP64 objective of the final labels: the paper's protocol of exactly 30
-iterations.  `value` = iterations executed / timed wall time, Gram included.
+Plain FP32 leg (the timed steps).  One step = one complete run of the method
+on the resident input: the Gram kernel K = kappa(X X^T) (FP32 MFMA, K stored
+FP32, 160 GB) followed by 30 reassignment steps (V in CSR form, SpMM row sweep
+of K, centroid norms, fused distance/argmin/histogram) and the FP64 objective
+of the final labels: the paper's protocol of exactly 30 iterations.
+`value` = iterations per second = 1 / the median time of one reassignment step
+over iterations 2..30 of the timed runs (HIP events on the launching stream;
+the Gram excluded); the rate with the Gram included is its own field.
 
 Also reported:
 * time-to-converge of the plain FP32 form from the random labels;
 * the mixed + learned form: BF16 Gram with K stored BF16 (80 GB), a feature
   network trained beforehand on 10^7 kernel-value pairs of the same mixture
-  (training time reported separately), k-means++ and Lloyd in feature space,
-  then exact refinement to convergence; its time-to-converge and the ARI of its
-  labels against the plain FP32 form converged from the same warm labels;
+  (training time reported separately), the warm start (k-means++ and Lloyd in
+  feature space, kkm_warm_start), then exact refinement to convergence; the
+  same BF16 form from the random labels as a control; speedups with and
+  without the training time;
+* the metric form against the FP64 oracle on the first 20000 points: every
+  precision pair refined from the same warm labels and compared with the
+  oracle converged from them (ARI, objective gap, iterations), and one step's
+  error report (max distance error, objective error, label flips);
+* the MNIST-shaped workload (n=60000, d=784, polynomial kernel, 30 iterations)
+  and the rings workload (n=1000): Gram and sweep rooflines, time per step;
 * roofline positions of the sweep (HBM) and the Gram (MFMA) from HIP-event
   timings of those launches, and HBM traffic from the recorded counters;
-* the FP64 oracle timed on the host on a bounded prefix of the workload.
+* the FP64 oracle timed on the host on the first 20000 points (K build and
+  loop apart, all host threads and one thread, median of 3), beside the GPU
+  on the same points.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows N]
-       [--no-cpu-baseline] [--no-converge] [--no-learned] [--copy-calibration]
+       [--no-cpu-baseline] [--no-converge] [--no-learned] [--no-batched]
+       [--cpu-full] [--copy-calibration] [--gram-shapes] [--learned-only]
+       [--batched-only]
 """
 import argparse
 import json
@@ -114,25 +127,101 @@ def ari(a, b):
     return 1.0 if mx == exp else (sij - exp) / (mx - exp)
 
 
-def cpu_baseline(w, rows, iters):
-    """The FP64 oracle on the first `rows` points: K from the definition and
-    `iters` fixed steps; time scaled to the full n by (n/rows)^2 (both parts
-    are O(n^2) at fixed d)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, rows, iters, full=False):
+    """The FP64 oracle as it stands on the first `rows` points, no scaling: the
+    K build (from the definition) and the loop (`iters` fixed steps) timed
+    apart, each the median of 3 runs, with all the host threads OpenMP uses and
+    with one thread.  With one thread the loop runs 3 steps per run (the rate
+    per step is what is compared) and the K build is timed only when `full`.
+    Returns (record, K)."""
+    import numpy as np
+
     import oracle
     X, _ = w.points(rows=rows)
     l0 = w.labels0(rows=rows)
-    t0 = time.perf_counter()
-    K = oracle.kernel_matrix(X, w.kernel, w.gamma, w.coef0, w.degree)
-    t1 = time.perf_counter()
-    oracle.fit(K, w.k, l0, iters, check_convergence=False)
-    t2 = time.perf_counter()
-    scale = (w.n / rows) ** 2
-    full_s = (t2 - t0) * scale
-    return {"value": iters / full_s, "unit": "iters/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": "first %d of the %d points, %d fixed iterations: K %.2f s + loop %.2f s; "
-                      "scaled by (n/%d)^2 = %.0f to the full workload" % (
-                          rows, w.n, iters, t1 - t0, t2 - t1, rows, scale)}
+    nthr = oracle.threads()
+
+    def timed(fn, reps=3):
+        ts, out = [], None
+        for _ in range(reps):
+            t = time.perf_counter()
+            out = fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)), out
+
+    kb, K = timed(lambda: oracle.kernel_matrix(X, w.kernel, w.gamma, w.coef0, w.degree))
+    loop, _ = timed(lambda: oracle.fit(K, w.k, l0, iters, check_convergence=False))
+    it1 = iters if full else 3
+    rec1 = {}
+    oracle.set_threads(1)
+    try:
+        loop1, _ = timed(lambda: oracle.fit(K, w.k, l0, it1, check_convergence=False))
+        rec1["loop_ms_per_iter"] = loop1 / it1 * 1e3
+        rec1["loop_iters_per_run"] = it1
+        if full:
+            kb1, _ = timed(lambda: oracle.kernel_matrix(X, w.kernel, w.gamma, w.coef0, w.degree))
+            rec1["k_build_s"] = kb1
+    finally:
+        oracle.set_threads(nthr)
+    rec = {"value": iters / loop, "unit": "iters/s", "cores": nthr, "kind": "oracle",
+           "sample": "first %d of the %d points, %d fixed iterations (no scaling): K build %.2f s, "
+                     "loop %.3f s per iteration, medians of 3, %d threads" % (
+                         rows, w.n, iters, kb, loop / iters, nthr),
+           "rows": rows, "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+           "all_threads": {"threads": nthr, "k_build_s": kb, "loop_ms_per_iter": loop / iters * 1e3},
+           "one_thread": rec1}
+    log("oracle on %d points: K %.2f s, %.2f ms per iteration (%d threads), %.1f ms per iteration "
+        "(1 thread)" % (rows, kb, loop / iters * 1e3, nthr, rec1["loop_ms_per_iter"]))
+    return rec, K
+
+
+def iter_spans(kkm, runs, per_run):
+    """Per-step durations (ms) of the recorded iterate launches: `runs` fixed-length
+    runs of `per_run` launches each (the steps, then the final objective pass),
+    iterations 2.. of every run."""
+    import numpy as np
+    sp = kkm.kkm_timing_spans("iterate")
+    if sp.size != runs * per_run:
+        raise RuntimeError("expected %d iterate launches, recorded %d" % (runs * per_run, sp.size))
+    return sp.reshape(runs, per_run)[:, 1:per_run - 1].ravel() if per_run > 2 else sp
+
+
+def gpu_same_prefix(kkm, torch, dev, w, rows, iters, reps=3):
+    """The plain FP32 form on the same first `rows` points as the oracle: per-step
+    median (iterations 2..30) and the Gram."""
+    import numpy as np
+    X, _ = w.points(rows=rows)
+    Xd = torch.from_numpy(X).to(dev)
+    ld = torch.from_numpy(w.labels0(rows=rows)).to(dev)
+    K = kkm.alloc_kernel_matrix(rows, kkm.F32, dev)
+
+    def run():
+        return kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, w.coef0, w.degree, max_iter=iters,
+                              check_convergence=False, K_ws=K)
+
+    run()
+    torch.cuda.synchronize()
+    kkm.kkm_timing_enable(True)
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    its = iter_spans(kkm, reps, iters + 1)
+    gram = kkm.kkm_timing_spans("gram")
+    kkm.kkm_timing_enable(False)
+    del K
+    med = float(np.median(its))
+    return {"rows": rows, "iter_ms": med, "iters_per_s": 1e3 / med, "gram_ms": float(np.median(gram))}
 
 
 def train_feature_map(kkm, torch, w, dev):
@@ -141,9 +230,10 @@ def train_feature_map(kkm, torch, w, dev):
     computed by the Gram kernel.  Returns (params, report)."""
     import datagen
     m = TRAIN_STEPS * TRAIN_BATCH
-    means = datagen.gmm_means(w.d, w.k, w.data_seed)
-    Xtr, _ = datagen.gmm(m, w.d, w.k, 0.5, w.data_seed + 30000, means=means)
-    params = torch.from_numpy(datagen.mlp_init_params(w.d, H1, H2, OUT, w.data_seed + 30002)).to(dev)
+    train_seed = w.data_seed + 30000 if w.train_seed is None else w.train_seed
+    init_seed = w.data_seed + 30002 if w.init_seed is None else w.init_seed
+    Xtr, _ = datagen.gmm(m, w.d, w.k, 0.5, train_seed, means=w.means())
+    params = torch.from_numpy(datagen.mlp_init_params(w.d, H1, H2, OUT, init_seed)).to(dev)
     mo, vo = torch.zeros_like(params), torch.zeros_like(params)
     Xd = torch.from_numpy(Xtr).to(dev)
     torch.cuda.synchronize()
@@ -160,63 +250,54 @@ def train_feature_map(kkm, torch, w, dev):
     return params, rep
 
 
-def warm_labels(kkm, w, params, Xd, seed, streams=WARM_STREAMS):
-    """phi_theta(X), then WARM_RESTARTS k-means++ seedings each followed by
-    Lloyd in feature space; keeps the labelling with the lowest feature-space
-    objective (the lowest restart index on ties).  Returns (labels, cheap
-    iterations summed over restarts).  The restarts are independent; they run
-    on `streams` HIP streams of default priority, one host thread each (the
-    library calls release the interpreter lock), and each restart computes
-    exactly what it computes alone."""
-    import threading
-
-    import torch
+def warm_uniforms(k, seed):
+    """The uniforms of the WARM_RESTARTS seedings: restart r draws with seed + r."""
+    import numpy as np
 
     import datagen
-    F = kkm.kkm_mlp_forward(params, Xd, H1, H2, OUT)
-    main = torch.cuda.current_stream()
-    ready = torch.cuda.Event()
-    ready.record(main)
-    out = [None] * WARM_RESTARTS
-    side = [torch.cuda.Stream() for _ in range(max(1, streams))]
-    errors = []
+    return np.stack([datagen.uniforms(k, seed + r) for r in range(WARM_RESTARTS)])
 
-    def worker(t):
-        try:
-            st = side[t]
-            with torch.cuda.stream(st):
-                st.wait_event(ready)
-                for r in range(t, WARM_RESTARTS, len(side)):
-                    _, seeded = kkm.kkm_feature_kmeanspp(F, w.k, datagen.uniforms(w.k, seed + r))
-                    lab, it, _, obj = kkm.kkm_feature_lloyd(F, w.k, seeded, max_iter=WARM_MAX_ITER,
-                                                            return_objective=True)
-                    out[r] = (obj, it, lab)
-        except Exception as e:  # re-raised on the calling thread
-            errors.append(e)
 
-    threads = [threading.Thread(target=worker, args=(t,)) for t in range(len(side))]
-    for th in threads:
-        th.start()
-    for th in threads:
-        th.join()
-    if errors:
-        raise errors[0]
-    for st in side:
-        main.wait_stream(st)
-    best = min(range(WARM_RESTARTS), key=lambda r: (out[r][0], r))
-    lab = out[best][2]
-    lab.record_stream(main)
-    return lab, sum(o[1] for o in out)
+def warm_labels(kkm, w, params, Xd, seed, streams=WARM_STREAMS):
+    """The learned warm start (kkm_warm_start): phi_theta(X), WARM_RESTARTS
+    k-means++ seedings each followed by Lloyd in feature space on `streams`
+    internal streams, the lowest feature-space objective kept.  Returns (labels,
+    cheap iterations summed over restarts)."""
+    r = kkm.kkm_warm_start(params, Xd, w.k, warm_uniforms(w.k, seed), max_iter=WARM_MAX_ITER,
+                           streams=streams, h1=H1, h2=H2, out=OUT)
+    return r["labels"], r["cheap_iters"]
+
+
+def timed_runs(torch, fn, reps=3):
+    """One untimed call, then `reps` timed ones; (median seconds, last result)."""
+    import numpy as np
+    fn()
+    out, ts = None, []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts)), out
+
+
+def speedups(plain_s, control_s, learned_s, train_s):
+    """Time-to-converge ratios of the learned form against plain FP32 and
+    against the same precision from random labels, without and with the
+    feature network's training time."""
+    return {"vs_plain_fp32": plain_s / learned_s, "vs_bf16_random_start": control_s / learned_s,
+            "vs_plain_fp32_incl_training": plain_s / (learned_s + train_s),
+            "vs_bf16_random_start_incl_training": control_s / (learned_s + train_s)}
 
 
 def learned_c5_leg(kkm, torch, dev):
     """The learned warm start on its own workload: phi_theta trained on 10^7
     kernel values of the 32-component mixture in R^128, then fresh n=100000
-    draws, k=32: plain FP32 from random labels against the BF16 form from the
-    learned warm start, both to convergence, and the FP32 form converged from
-    the same warm labels as the reference for the result (ARI)."""
-    import numpy as np
-
+    draws, k=32, all to convergence: plain FP32 from random labels, the BF16
+    form from the same random labels (the control), the BF16 form from the
+    learned warm start, and the FP32 form from the warm start (the reference
+    for the result, ARI; and the exact iterations at equal precision)."""
     import datagen
     w = datagen.WORKLOADS["learned100k"]
     X, truth = w.points()
@@ -226,21 +307,12 @@ def learned_c5_leg(kkm, torch, dev):
     params, train_rep = train_feature_map(kkm, torch, w, dev)
     K = kkm.alloc_kernel_matrix(n, kkm.F32, dev)
     lab = torch.empty(n, dtype=torch.int32, device=dev)
-
-    def plain_run():
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        r = kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, max_iter=w.max_iter, check_convergence=True,
-                           K_ws=K, labels_out=lab)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t, r
-
-    plain_run()
-    pr = [plain_run() for _ in range(3)]
-    plain_s = float(np.median([x[0] for x in pr]))
-    rp = pr[-1][1]
-    plain_labels = lab.cpu().numpy()
     useed = w.label_seed + 30003
+
+    plain_s, rp = timed_runs(torch, lambda: kkm.kkm_fit_ex(
+        Xd, w.k, ld, w.kernel, w.gamma, max_iter=w.max_iter, check_convergence=True, K_ws=K,
+        labels_out=lab))
+    plain_labels = lab.cpu().numpy()
     warm, _ = warm_labels(kkm, w, params, Xd, useed)
     ref = kkm.kkm_fit_ex(Xd, w.k, warm, w.kernel, w.gamma, max_iter=w.max_iter, check_convergence=True,
                          K_ws=K, labels_out=lab)
@@ -249,44 +321,199 @@ def learned_c5_leg(kkm, torch, dev):
     torch.cuda.empty_cache()
     K16 = kkm.alloc_kernel_matrix(n, kkm.BF16, dev)
     lab16 = torch.empty(n, dtype=torch.int32, device=dev)
+    control_s, rc = timed_runs(torch, lambda: kkm.kkm_fit_ex(
+        Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16, max_iter=w.max_iter,
+        check_convergence=True, K_ws=K16, labels_out=lab16))
+    control_labels = lab16.cpu().numpy()
 
     def learned_run():
-        torch.cuda.synchronize()
         ta = time.perf_counter()
         wl, ch = warm_labels(kkm, w, params, Xd, useed)
-        torch.cuda.synchronize()
         tb = time.perf_counter()
         r = kkm.kkm_fit_ex(Xd, w.k, wl, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
                            max_iter=w.max_iter, check_convergence=True, K_ws=K16, labels_out=lab16)
-        torch.cuda.synchronize()
-        return time.perf_counter() - ta, tb - ta, ch, r
+        return tb - ta, ch, r
 
-    learned_run()
-    lr = [learned_run() for _ in range(3)]
-    secs = float(np.median([x[0] for x in lr]))
-    _, _, ch, r = lr[-1]
+    secs, (ws_s, ch, r) = timed_runs(torch, learned_run)
     ml = lab16.cpu().numpy()
     del K16
     torch.cuda.empty_cache()
     rec = {
-        "workload": "learned100k: fresh draws n=%d of the 32-component mixture in R^%d (sigma 0.5), "
-                    "k=%d, gaussian gamma=1/%d" % (n, w.d, w.k, w.d),
+        "workload": "learned100k: fresh draws n=%d of the 32-component mixture in R^%d (sigma 0.5; "
+                    "means seed 5000, training draws 5001, points 5002, labels 5003), k=%d, "
+                    "gaussian gamma=1/%d" % (n, w.d, w.k, w.d),
         "training": train_rep,
         "plain_fp32": {"seconds": plain_s, "iters": rp["iters"], "objective": rp["objective"],
                        "gram_ms": rp["times_ms"][0], "ari_vs_truth": ari(plain_labels, truth)},
-        "mixed_learned": {"seconds": secs, "warm_start_seconds": float(np.median([x[1] for x in lr])),
+        "bf16_random_start": {"seconds": control_s, "iters": rc["iters"], "objective": rc["objective"],
+                              "gram_ms": rc["times_ms"][0], "ari_vs_truth": ari(control_labels, truth)},
+        "mixed_learned": {"seconds": secs, "warm_start_seconds": ws_s,
                           "cheap_iters": ch, "exact_iters": r["iters"], "objective": r["objective"],
                           "gram_ms": r["times_ms"][0], "ari_vs_truth": ari(ml, truth),
                           "ari_vs_fp32_from_same_warm_start": ari(ml, ref_labels)},
         "fp32_from_warm_start": {"iters": ref["iters"], "objective": ref["objective"]},
-        "exact_iters_saved": rp["iters"] - r["iters"],
+        "exact_iters_saved_fp32": rp["iters"] - ref["iters"],
+        "exact_iters_saved_bf16": rc["iters"] - r["iters"],
         "objective_rel_gap_vs_plain": (r["objective"] - rp["objective"]) / abs(rp["objective"]),
-        "speedup_time_to_converge_vs_plain": plain_s / secs,
+        "speedup_time_to_converge": speedups(plain_s, control_s, secs, train_rep["seconds"]),
     }
-    log("learned100k: plain %.3f s (%d iters, J %.2f), mixed+learned %.3f s (%d cheap + %d exact, J %.2f), "
-        "ARI vs FP32 from same start %.4f" % (plain_s, rp["iters"], rp["objective"], secs, ch, r["iters"],
-                                              r["objective"], rec["mixed_learned"]["ari_vs_fp32_from_same_warm_start"]))
+    log("learned100k: plain %.3f s (%d iters, J %.2f), bf16 random start %.3f s (%d iters), "
+        "mixed+learned %.3f s (%d cheap + %d exact, J %.2f), ARI vs FP32 from same start %.4f" % (
+            plain_s, rp["iters"], rp["objective"], control_s, rc["iters"], secs, ch, r["iters"],
+            r["objective"], rec["mixed_learned"]["ari_vs_fp32_from_same_warm_start"]))
     return rec
+
+
+def fixed_iteration_leg(kkm, torch, dev, w, reps=3):
+    """The plain FP32 form on workload w with its fixed iteration count: Gram
+    and sweep rooflines and the per-step time (iterations 2.. of each run)."""
+    import numpy as np
+    X, truth = w.points()
+    n = w.n
+    Xd = torch.from_numpy(X).to(dev)
+    ld = torch.from_numpy(w.labels0()).to(dev)
+    K = kkm.alloc_kernel_matrix(n, kkm.F32, dev)
+    lab = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def run():
+        return kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, w.coef0, w.degree, max_iter=w.max_iter,
+                              check_convergence=False, K_ws=K, labels_out=lab)
+
+    run()
+    torch.cuda.synchronize()
+    kkm.kkm_timing_enable(True)
+    for _ in range(reps):
+        r = run()
+    torch.cuda.synchronize()
+    its = iter_spans(kkm, reps, w.max_iter + 1)
+    gram = float(np.median(kkm.kkm_timing_spans("gram")))
+    sweep = float(np.median(kkm.kkm_timing_spans("sweep")))
+    kkm.kkm_timing_enable(False)
+    labels = lab.cpu().numpy()
+    del K
+    torch.cuda.empty_cache()
+    flops = float(n) * (n + 1) * w.d
+    kbytes = float(n) * n * 4
+    med = float(np.median(its))
+    return {"n": n, "d": w.d, "k": w.k, "iterations": w.max_iter, "objective": r["objective"],
+            "ari_vs_truth": ari(labels, truth),
+            "iter_ms": med, "iters_per_s": 1e3 / med,
+            "gram": {"kernel": "gram_f32_mfma", "avg_ms": gram, "algorithmic_flops": flops,
+                     "achieved_tflops": flops / (gram * 1e-3) / 1e12,
+                     "frac": flops / (gram * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFS},
+            "sweep": {"kernel": "spmm_row_sweep", "avg_ms": sweep, "algorithmic_bytes": kbytes,
+                      "achieved_gbs": kbytes / (sweep * 1e-3) / 1e9,
+                      "frac": kbytes / (sweep * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
+def mnist_leg(kkm, torch, dev):
+    """The MNIST-shaped stand-in: n=60000, d=784, k=10, polynomial (x.y+1)^2,
+    30 fixed iterations, FP32 Gram and K (14.4 GB)."""
+    import datagen
+    w = datagen.WORKLOADS["mnist_like"]
+    rec = fixed_iteration_leg(kkm, torch, dev, w)
+    rec["workload"] = ("mnist_like: 10 means U[0,1]^784, points clipped to [0,1], 80% of entries "
+                       "zeroed; polynomial (x.y+1)^2")
+    rec["targets"] = {"gram_ms_at_0.6_mfma": float(w.n) * (w.n + 1) * w.d / (0.6 * FP32_MFMA_PEAK_TFS * 1e12) * 1e3,
+                      "sweep_ms_at_0.7_hbm": float(w.n) * w.n * 4 / (0.7 * HBM_PEAK_GBS * 1e9) * 1e3}
+    log("mnist_like: gram %.2f ms (%.3f of FP32 MFMA), sweep %.3f ms (%.3f of HBM), %.3f ms per step" % (
+        rec["gram"]["avg_ms"], rec["gram"]["frac"], rec["sweep"]["avg_ms"], rec["sweep"]["frac"],
+        rec["iter_ms"]))
+    return rec
+
+
+def rings_leg(kkm, torch, dev, reps=5):
+    """The rings workload (n=1000, k=4, Gaussian gamma=1): to convergence, the
+    time per step in microseconds (K is 4 MB: launch and latency bound)."""
+    import numpy as np
+
+    import datagen
+    w = datagen.WORKLOADS["rings"]
+    X, truth = w.points()
+    Xd = torch.from_numpy(X).to(dev)
+    ld = torch.from_numpy(w.labels0()).to(dev)
+
+    def run():
+        return kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, max_iter=w.max_iter,
+                              check_convergence=True)
+
+    secs, r = timed_runs(torch, run, reps)
+    kkm.kkm_timing_enable(True)
+    run()
+    torch.cuda.synchronize()
+    its = kkm.kkm_timing_spans("iterate")
+    kkm.kkm_timing_enable(False)
+    med = float(np.median(its[1:]))
+    return {"workload": "rings: n=1000, d=16, four rings, k=4, gaussian gamma=1",
+            "iters": r["iters"], "objective": r["objective"],
+            "ari_vs_truth": ari(r["labels"].cpu().numpy(), truth),
+            "us_per_iter": med * 1e3, "seconds_to_converge": secs}
+
+
+def error_report(K_or, k, labels_in, orc, D, J):
+    """One step's error against the oracle's step from the same labels: the
+    largest distance error over the condition scale sigma_i = |K_ii| +
+    max_c (2|E_ic| + |C_c|), the relative objective error and the fraction of
+    labels that differ."""
+    import numpy as np
+    n = K_or.shape[0]
+    V = np.zeros((n, k))
+    V[np.arange(n), labels_in] = 1.0
+    cnt = V.sum(0)
+    S = K_or @ V
+    live = cnt > 0
+    E = np.where(live, S / np.maximum(cnt, 1), 0.0)
+    C = np.where(live, (V * S).sum(0) / np.maximum(cnt, 1) ** 2, 0.0)
+    sig = np.abs(np.diag(K_or)) + (2 * np.abs(E[:, live]) + np.abs(C[live])).max(axis=1)
+    fin = np.isfinite(orc["D"])
+    err = np.where(fin, np.abs(D.astype(np.float64) - np.where(fin, orc["D"], 0.0)), 0.0)
+    return {"max_dist_err_over_sigma": float((err / sig[:, None]).max()),
+            "objective_rel_err": abs(J - orc["J_in"]) / abs(orc["J_in"])}
+
+
+def metric_check_20k(kkm, torch, dev, w, rows, params, K_or, seed):
+    """The metric form against the FP64 oracle on the first `rows` points: the
+    learned warm start of these points, every precision pair refined from it to
+    convergence and compared with the oracle converged from the same labels,
+    and one step from the warm labels against the oracle's step."""
+    import oracle
+    X, truth = w.points(rows=rows)
+    Xd = torch.from_numpy(X).to(dev)
+    warm, _ = warm_labels(kkm, w, params, Xd, seed)
+    warm_h = warm.cpu().numpy()
+    t = time.perf_counter()
+    ref = oracle.fit(K_or, w.k, warm_h, 300)
+    orc = oracle.step(K_or, w.k, warm_h, want_gap=False)
+    log("oracle from warm labels on %d points: %d iterations, J %.6f (%.1f s)" % (
+        rows, ref["iters"], ref["objective"], time.perf_counter() - t))
+    pairs = (("f32/f32", kkm.F32, kkm.F32), ("bf16/f32", kkm.BF16, kkm.F32),
+             ("bf16/bf16", kkm.BF16, kkm.BF16), ("fp8/f32", kkm.FP8_ROWSCALED, kkm.F32),
+             ("fp8/bf16", kkm.FP8_ROWSCALED, kkm.BF16))
+    forms = {}
+    for name, gp, ks in pairs:
+        r = kkm.kkm_fit_ex(Xd, w.k, warm, w.kernel, w.gamma, gram_prec=gp, k_store=ks, max_iter=300,
+                           check_convergence=True)
+        lab = r["labels"].cpu().numpy()
+        J_or_of_gpu = oracle.objective(K_or, w.k, lab)
+        K, dg = kkm.kkm_gram(Xd, w.kernel, w.gamma, gram_prec=gp, k_store=ks)
+        lo, _, _, Jin, D, _ = kkm.kkm_iterate(K, dg, warm, w.k, D_out=True)
+        torch.cuda.synchronize()
+        rep = error_report(K_or, w.k, warm_h, orc, D.cpu().numpy(), float(Jin.item()))
+        rep["step_label_flip_frac"] = float((lo.cpu().numpy() != orc["labels"]).mean())
+        del K, D
+        rep.update({"ari_vs_oracle_from_same_warm_start": ari(lab, ref["labels"]),
+                    "exact_iters": r["iters"], "oracle_iters": ref["iters"],
+                    "objective_gap_rel": (J_or_of_gpu - ref["objective"]) / abs(ref["objective"]),
+                    "ari_vs_truth": ari(lab, truth)})
+        forms[name] = rep
+        log("  %s: ARI vs oracle %.4f, %d vs %d iterations, J gap %.2e, step: max dD/sigma %.2e, "
+            "dJ/J %.2e, flips %.4f" % (name, rep["ari_vs_oracle_from_same_warm_start"], r["iters"],
+                                      ref["iters"], rep["objective_gap_rel"],
+                                      rep["max_dist_err_over_sigma"], rep["objective_rel_err"],
+                                      rep["step_label_flip_frac"]))
+    torch.cuda.empty_cache()
+    return {"rows": rows, "oracle_iters": ref["iters"], "oracle_objective": ref["objective"],
+            "oracle_ari_vs_truth": ari(ref["labels"], truth), "forms": forms}
 
 
 def batched_leg(kkm, torch, dev, iters):
@@ -415,12 +642,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rows", type=int, default=0, help="use only the first N points (0 = all)")
     ap.add_argument("--iters", type=int, default=0, help="override the 30 fixed iterations")
-    ap.add_argument("--cpu-rows", type=int, default=24000)
+    ap.add_argument("--cpu-rows", type=int, default=20000)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle's K build and every loop iteration at one thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the MNIST-shaped and rings legs")
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the learned warm start on its n=100000, k=32 workload")
     ap.add_argument("--batched-only", action="store_true",
@@ -440,19 +671,18 @@ def main():
     import datagen
     import paper_2501_05587_amd as kkm
 
+    dev = torch.device("cuda:0")
     if args.copy_calibration:
         copy_calibration()
         return
     if args.gram_shapes:
-        print(json.dumps({"gram_shapes": gram_shapes(kkm, torch, torch.device("cuda:0"))}),
-              flush=True)
+        print(json.dumps({"gram_shapes": gram_shapes(kkm, torch, dev)}), flush=True)
         return
     if args.learned_only:
-        print(json.dumps(learned_c5_leg(kkm, torch, torch.device("cuda:0"))), flush=True)
+        print(json.dumps(learned_c5_leg(kkm, torch, dev)), flush=True)
         return
     if args.batched_only:
-        print(json.dumps(batched_leg(kkm, torch, torch.device("cuda:0"), args.iters or 30)),
-              flush=True)
+        print(json.dumps(batched_leg(kkm, torch, dev, args.iters or 30)), flush=True)
         return
 
     w = datagen.WORKLOADS["gmm200k"]
@@ -464,7 +694,6 @@ def main():
     l0 = w.labels0(rows=n)
     log("data generated in %.1f s" % (time.perf_counter() - t))
 
-    dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
     ld = torch.from_numpy(l0).to(dev)
     K = kkm.alloc_kernel_matrix(n, kkm.F32, dev)
@@ -492,11 +721,12 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tim = kkm.kkm_timing_read()
+    step_spans = iter_spans(kkm, args.steps, iters + 1)
     kkm.kkm_timing_enable(False)
     wall = t1 - t0
     total_iters = sum(r["iters"] for r in rs)
     gram_ms = float(np.mean([r["times_ms"][0] for r in rs]))
-    iter_ms = float(np.mean([r["times_ms"][1] / max(r["iters"], 1) for r in rs]))
+    iter_ms = float(np.median(step_spans))
 
     sweep_ms = tim["sweep"][0] / max(tim["sweep"][1], 1)
     sweep_bytes = float(n) * n * 4  # K read once per sweep
@@ -530,9 +760,10 @@ def main():
 
     # ------------------------------------------------------------ mixed + learned
     learned = None
+    params = None
+    useed = w.label_seed + 30003
     if not args.no_learned and not args.no_converge:
         params, train_rep = train_feature_map(kkm, torch, w, dev)
-        useed = w.label_seed + 30003
         # reference: the plain FP32 form converged from the same warm labels
         warm, cheap = warm_labels(kkm, w, params, Xd, useed)
         ref = kkm.kkm_fit_ex(Xd, w.k, warm, w.kernel, w.gamma, max_iter=300, check_convergence=True,
@@ -545,19 +776,21 @@ def main():
         lab16 = torch.empty(n, dtype=torch.int32, device=dev)
 
         def mixed_learned():
-            torch.cuda.synchronize()
             ta = time.perf_counter()
             wl, ch = warm_labels(kkm, w, params, Xd, useed)
-            torch.cuda.synchronize()
             tb = time.perf_counter()
             r = kkm.kkm_fit_ex(Xd, w.k, wl, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
                                max_iter=300, check_convergence=True, K_ws=K16, labels_out=lab16)
-            torch.cuda.synchronize()
-            return time.perf_counter() - ta, tb - ta, ch, r
+            return tb - ta, ch, r
+
+        def control():
+            # the same precision from the random labels
+            return kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16,
+                                  k_store=kkm.BF16, max_iter=300, check_convergence=True, K_ws=K16,
+                                  labels_out=lab16)
 
         def kernel_seeded():
             # the non-learned warm start: k-means++ on the exact kernel matrix
-            torch.cuda.synchronize()
             ta = time.perf_counter()
             Kg, dg = kkm.kkm_gram(Xd, w.kernel, w.gamma, w.coef0, w.degree, gram_prec=kkm.BF16,
                                   k_store=kkm.BF16, K=K16)
@@ -565,45 +798,45 @@ def main():
             torch.cuda.synchronize()
             tb = time.perf_counter()
             r = kkm.kkm_refine(Kg, dg, w.k, lab0, max_iter=300, labels_out=lab16)
-            torch.cuda.synchronize()
-            return time.perf_counter() - ta, tb - ta, r
+            return tb - ta, r
 
-        kernel_seeded()
-        kruns = [kernel_seeded() for _ in range(3)]
-        ks_secs = float(np.median([x[0] for x in kruns]))
-        _, _, kr = kruns[-1]
+        control_s, rcn = timed_runs(torch, control)
+        control_labels = lab16.cpu().numpy()
+        ks_secs, (ks_seed_s, kr) = timed_runs(torch, kernel_seeded)
         ks_labels = lab16.cpu().numpy()
-        kseeded = {"seconds": ks_secs, "gram_and_seeding_seconds": float(np.median([x[1] for x in kruns])),
+        kseeded = {"seconds": ks_secs, "gram_and_seeding_seconds": ks_seed_s,
                    "exact_iters": kr["iters"], "objective": kr["objective"],
                    "ari_vs_truth": ari(ks_labels, truth),
                    "empty_clusters": int((np.bincount(ks_labels, minlength=w.k) == 0).sum())}
         log("kernel k-means++ + exact: %.3f s (Gram + seeding %.3f s, %d exact iterations), J=%.3f" % (
-            ks_secs, kseeded["gram_and_seeding_seconds"], kr["iters"], kr["objective"]))
+            ks_secs, ks_seed_s, kr["iters"], kr["objective"]))
 
-        mixed_learned()  # warm-up of the whole leg
-        runs = [mixed_learned() for _ in range(3)]
-        secs = float(np.median([x[0] for x in runs]))
-        _, _, ch, r = runs[-1]
+        secs, (ws_s, ch, r) = timed_runs(torch, mixed_learned)
         ml_labels = lab16.cpu().numpy()
         # per-iteration rate of the mixed form: 30 fixed iterations on the BF16 K
         kkm.kkm_timing_enable(True)
-        rf = kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
-                            max_iter=iters, check_convergence=False, K_ws=K16, labels_out=lab16)
+        kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
+                       max_iter=iters, check_convergence=False, K_ws=K16, labels_out=lab16)
         torch.cuda.synchronize()
         tim16 = kkm.kkm_timing_read()
+        it16 = float(np.median(iter_spans(kkm, 1, iters + 1)))
         kkm.kkm_timing_enable(False)
         sw16 = tim16["sweep"][0] / max(tim16["sweep"][1], 1)
         g16 = tim16["gram"][0] / max(tim16["gram"][1], 1)
         learned = {
-            "seconds": secs, "warm_start_seconds": float(np.median([x[1] for x in runs])),
+            "seconds": secs, "warm_start_seconds": ws_s,
             "cheap_iters": ch, "exact_iters": r["iters"], "objective": r["objective"],
             "gram": "bf16 mfma", "k_store": "bf16", "gram_ms": r["times_ms"][0],
-            "iter_ms": rf["times_ms"][1] / max(rf["iters"], 1),
-            "iters_per_s": rf["iters"] / (rf["times_ms"][1] * 1e-3),
+            "iter_ms": it16, "iters_per_s": 1e3 / it16,
             "ari_vs_fp32_from_same_warm_start": ari(ml_labels, ref_labels),
             "ari_vs_truth": ari(ml_labels, truth),
             "empty_clusters": int((np.bincount(ml_labels, minlength=w.k) == 0).sum()),
             "fp32_from_warm_start": {"iters": ref["iters"], "objective": ref["objective"]},
+            "bf16_random_start": {"seconds": control_s, "iters": rcn["iters"],
+                                  "objective": rcn["objective"],
+                                  "ari_vs_truth": ari(control_labels, truth)},
+            "exact_iters_saved_fp32": (plain["iters"] - ref["iters"]) if plain else None,
+            "exact_iters_saved_bf16": rcn["iters"] - r["iters"],
             "sweep_bf16": {"avg_ms": sw16, "achieved_gbs": float(n) * n * 2 / (sw16 * 1e-3) / 1e9,
                            "frac_hbm": float(n) * n * 2 / (sw16 * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "gram_bf16": {"avg_ms": g16, "achieved_tflops": gram_flops / (g16 * 1e-3) / 1e12,
@@ -612,20 +845,37 @@ def main():
             "kernel_kmeanspp_warm_start": kseeded,
         }
         if plain:
-            learned["speedup_time_to_converge_vs_plain"] = plain["seconds"] / secs
+            learned["speedup_time_to_converge"] = speedups(plain["seconds"], control_s, secs,
+                                                           train_rep["seconds"])
         log("mixed+learned: %.3f s (warm start %.3f s, %d cheap + %d exact iterations), ARI vs FP32 "
-            "from same start %.4f" % (secs, learned["warm_start_seconds"], ch, r["iters"],
-                                       learned["ari_vs_fp32_from_same_warm_start"]))
+            "from same start %.4f; bf16 from random labels %.3f s (%d iterations)" % (
+                secs, ws_s, ch, r["iters"], learned["ari_vs_fp32_from_same_warm_start"], control_s,
+                rcn["iters"]))
         del K16
     else:
         del K
     torch.cuda.empty_cache()
+    small = None
+    if not args.no_small:
+        small = {"mnist_like": mnist_leg(kkm, torch, dev), "rings": rings_leg(kkm, torch, dev)}
     batched = None if args.no_batched else batched_leg(kkm, torch, dev, iters)
     learned_c5 = None if (args.no_learned or args.no_converge) else learned_c5_leg(kkm, torch, dev)
 
+    cpu = None
+    same_prefix = None
+    metric_20k = None
+    if not args.no_cpu_baseline:
+        rows = min(args.cpu_rows, n)
+        cpu, K_or = cpu_baseline(w, rows, iters, full=args.cpu_full)
+        same_prefix = gpu_same_prefix(kkm, torch, dev, w, rows, iters)
+        cpu["gpu_same_rows"] = same_prefix
+        if params is not None:
+            metric_20k = metric_check_20k(kkm, torch, dev, w, rows, params, K_or, useed)
+        del K_or
+
     out = {
         "metric": METRIC,
-        "value": total_iters / wall,
+        "value": 1e3 / iter_ms,
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -640,18 +890,22 @@ def main():
                    "n": n, "d": w.d, "k": w.k, "kernel": "gaussian gamma=1/%d" % w.d,
                    "iterations_per_step": iters, "gram": "f32 mfma", "k_store": "f32",
                    "parallelism": "single gpu"},
+        "value_definition": "1 / median time of one reassignment step, iterations 2..%d of the "
+                            "timed runs, Gram excluded" % iters,
+        "iters_per_s_incl_gram": total_iters / wall,
         "gram_ms": gram_ms,
         "iter_ms": iter_ms,
         "plain_fp32_to_convergence": plain,
         "mixed_learned_to_convergence": learned,
+        "metric_form_vs_oracle_20k": metric_20k,
+        "mnist_like_60k": small and small["mnist_like"],
+        "rings_1k": small and small["rings"],
         "batched": batched,
         "learned_warm_start_100k": learned_c5,
         "roofline": roof,
         "roofline_gram": roof_g,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_rows, n), iters)
     print(json.dumps(out), flush=True)
 
 

@@ -145,6 +145,12 @@ class Workload:
     check_convergence: bool
     data_seed: int
     label_seed: int
+    means_seed: int | None = None  # the mixture's means (default: data_seed)
+    train_seed: int | None = None  # fresh training draws of the same mixture
+    init_seed: int | None = None   # initial parameters of the feature network
+
+    def means(self):
+        return gmm_means(self.d, self.k, self.data_seed if self.means_seed is None else self.means_seed)
 
     def points(self, rows: int | None = None):
         rows = self.n if rows is None else rows
@@ -154,7 +160,7 @@ class Workload:
         if self.name == "mnist_like":
             return mnist_like(n=self.n, d=self.d, seed=self.data_seed, rows=rows)
         if self.name in ("gmm200k", "learned100k"):
-            return gmm(self.n, self.d, self.k, 0.5, self.data_seed, rows=rows)
+            return gmm(self.n, self.d, self.k, 0.5, self.data_seed, means=self.means(), rows=rows)
         raise KeyError(self.name)
 
     def labels0(self, rows: int | None = None):
@@ -167,9 +173,10 @@ WORKLOADS = {
     "mnist_like": Workload("mnist_like", 60000, 784, 10, POLY, 1.0, 1.0, 2, 30, False, 2, 102),
     "gmm200k": Workload("gmm200k", 200000, 1024, 64, GAUSS, 1.0 / 1024, 0.0, 1, 30, False, 3, 103),
     # the learned warm-start test set: fresh draws of the 32-component mixture
-    # in R^128 (sigma 0.5) that the feature network is trained on
-    "learned100k": Workload("learned100k", 100000, 128, 32, GAUSS, 1.0 / 128, 0.0, 1, 300, True, 5,
-                            105),
+    # in R^128 (sigma 0.5) that the feature network is trained on; means seed
+    # 5000, training draws 5001, test points 5002, initial labels 5003
+    "learned100k": Workload("learned100k", 100000, 128, 32, GAUSS, 1.0 / 128, 0.0, 1, 300, True,
+                            5002, 5003, means_seed=5000, train_seed=5001, init_seed=5005),
 }
 
 

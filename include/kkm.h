@@ -298,6 +298,15 @@ kkm_status kkm_mlp_forward(const float *params, int64_t d, int64_t h1, int64_t h
                            void *ws, size_t ws_bytes, void *stream);
 size_t kkm_mlp_forward_workspace_bytes(int64_t n, int64_t d, int64_t h1, int64_t h2, int64_t out);
 
+/* kkm_mlp_forward with every layer's output: H1 [n, h1] = GELU(X W1^T + b1),
+ * H2 [n, h2] = GELU(H1 W2^T + b2) (row strides h1 and h2, FP32, device) and
+ * F [n, ldf] = H2 W3^T + b3, the same values kkm_mlp_forward computes (each
+ * product rounds its operands to bfloat16 and accumulates in FP32), for
+ * checking the layers one at a time.  No workspace.  Asynchronous. */
+kkm_status kkm_mlp_forward_layers(const float *params, int64_t d, int64_t h1, int64_t h2,
+                                  int64_t out, const float *X, int64_t n, int64_t ldx, float *H1,
+                                  float *H2, float *F, int64_t ldf, void *stream);
+
 /* Loss L = (1/B^2) ||Phi Phi^T - KB||_F^2 of a batch XB [B, ldx] with kernel
  * values KB [B, ldkb] (symmetric), and dL/dparams into grad (param_count
  * floats, device).  *loss is a device double.  Asynchronous.  Workspace: at
@@ -386,6 +395,42 @@ kkm_status kkm_kernel_kmeanspp(const void *K, int32_t k_store, int64_t ldk, cons
                                int32_t *labels_out, void *ws, size_t ws_bytes, void *stream);
 size_t kkm_kernel_kmeanspp_workspace_bytes(int64_t n, int32_t k);
 
+/* kkm_warm_start — the learned warm start in one call (replacing the random
+ * initial labels of Sec. 3.4): F = phi_theta(X) as kkm_mlp_forward computes it,
+ * then `restarts` independent k-means++ seedings (the D^2 sampling of Sec.
+ * 2.1, as kkm_feature_kmeanspp) each followed by at most max_iter Lloyd steps
+ * in feature space (as kkm_feature_lloyd, Sec. 2.1's three phases with
+ * explicit centroids), and the labelling whose feature-space objective (the
+ * `objective` of kkm_feature_lloyd) is lowest; ties, and restarts whose
+ * objective is NaN, go to the lowest restart index.  kkm_fit_ex then refines
+ * labels_out exactly.
+ *
+ *   params, d, h1, h2, out   the network, as kkm_mlp_forward.
+ *   X [n, ldx]    float32 points (device).
+ *   k             clusters, 1 <= k <= min(n, KKM_MAX_K).
+ *   restarts      >= 1 seedings; restart r draws with uniforms[r*k .. r*k+k)
+ *                 (host double, each in [0, 1)).
+ *   max_iter      >= 0 Lloyd steps per restart.
+ *   streams       >= 1: the restarts run on this many internal streams of
+ *                 default priority, one host thread each; the result is the
+ *                 same for every value.
+ *   labels_out    [n] int32 (device) the chosen labelling.
+ *   objective, cheap_iters, best_restart   host, nullable: the chosen
+ *                 restart's feature-space objective, the Lloyd steps summed
+ *                 over all restarts, and the chosen restart's index.
+ *   ws, ws_bytes  at least kkm_warm_start_workspace_bytes(n, d, h1, h2, out,
+ *                 k, streams) bytes of device workspace.
+ * Synchronises `stream` before returning.  Errors: KKM_ERR_ARG (sizes, NULL
+ * pointers, a uniform outside [0, 1)), KKM_ERR_NOMEM (small workspace),
+ * KKM_ERR_UNSUPPORTED (k > KKM_MAX_K), or the error of a failing restart. */
+kkm_status kkm_warm_start(const float *params, int64_t d, int64_t h1, int64_t h2, int64_t out,
+                          const float *X, int64_t n, int64_t ldx, int32_t k, int32_t restarts,
+                          const double *uniforms, int32_t max_iter, int32_t streams,
+                          int32_t *labels_out, double *objective, int32_t *cheap_iters,
+                          int32_t *best_restart, void *ws, size_t ws_bytes, void *stream);
+size_t kkm_warm_start_workspace_bytes(int64_t n, int64_t d, int64_t h1, int64_t h2, int64_t out,
+                                      int32_t k, int32_t streams);
+
 /*
  * Launch timing for benchmarks (process-wide).  kkm_timing_enable(1) clears
  * the records and starts bracketing every Gram launch, every SpMM sweep launch
@@ -397,6 +442,13 @@ size_t kkm_kernel_kmeanspp_workspace_bytes(int64_t n, int32_t k);
  */
 kkm_status kkm_timing_enable(int32_t on);
 kkm_status kkm_timing_read(double *total_ms, int64_t *launches);
+
+/* kkm_timing_spans — the individual durations (milliseconds, launch order) of
+ * the launches of class cls (0: Gram, 1: sweep, 2: iterate step) recorded since
+ * timing was enabled: ms (host double [cap]) receives the first min(cap,
+ * *count) of them and *count (host) their number.  Waits for the recorded
+ * events.  KKM_ERR_ARG for an unknown class or a NULL output. */
+kkm_status kkm_timing_spans(int32_t cls, double *ms, int64_t cap, int64_t *count);
 
 /* Message for the last error on this thread ("" if none). */
 const char *kkm_last_error(void);

@@ -38,6 +38,8 @@ def lib():
         L = ctypes.CDLL(path)
         L.oracle_threads.restype = _int
         L.oracle_threads.argtypes = []
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [_int]
         L.oracle_kappa.restype = _d
         L.oracle_kappa.argtypes = [_f32p, _f32p, _i64, _int, _d, _d, _int]
         L.oracle_kernel_matrix.restype = None
@@ -65,6 +67,11 @@ def lib():
 def threads() -> int:
     """Number of OpenMP threads the oracle's loops use."""
     return int(lib().oracle_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads of the oracle's following OpenMP loops (timing only)."""
+    lib().oracle_set_threads(int(t))
 
 
 def _ptr(a):

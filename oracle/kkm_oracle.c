@@ -48,6 +48,8 @@ enum { OR_LINEAR = 0, OR_POLY = 1, OR_GAUSS = 2 };
 
 /* Threads the OpenMP loops use (reported with the CPU timings). */
 int oracle_threads(void) { return omp_get_max_threads(); }
+/* Sets the threads of the following OpenMP loops (for timing at one thread). */
+void oracle_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
 enum { OR_EMPTY_INF = 0, OR_EMPTY_ZERO_CENTROID = 1 };
 
 /* kappa(x, y) from the definitions of Sec. 3.2 (and the inner product). */

@@ -30,7 +30,8 @@ EXPORTS = ("kkm_gram", "kkm_gram_ex", "kkm_gram_workspace_bytes", "kkm_iterate",
            "kkm_mlp_train_fresh", "kkm_mlp_train_fresh_workspace_bytes",
            "kkm_fit_batched", "kkm_fit_batched_workspace_bytes",
            "kkm_kernel_kmeanspp", "kkm_kernel_kmeanspp_workspace_bytes", "kkm_refine",
-           "kkm_timing_enable", "kkm_timing_read", "kkm_last_error")
+           "kkm_warm_start", "kkm_warm_start_workspace_bytes", "kkm_mlp_forward_layers",
+           "kkm_timing_enable", "kkm_timing_read", "kkm_timing_spans", "kkm_last_error")
 
 
 class KKMError(RuntimeError):
@@ -88,6 +89,9 @@ def lib():
         L.kkm_mlp_forward.restype = ctypes.c_int
         L.kkm_mlp_forward.argtypes = [_vp, _i64, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _vp,
                                       _sz, _vp]
+        L.kkm_mlp_forward_layers.restype = ctypes.c_int
+        L.kkm_mlp_forward_layers.argtypes = [_vp, _i64, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _vp,
+                                             _vp, _i64, _vp]
         L.kkm_mlp_loss_grad.restype = ctypes.c_int
         L.kkm_mlp_loss_grad.argtypes = [_vp, _i64, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64,
                                         _vp, _vp, _vp, _sz, _vp]
@@ -125,10 +129,18 @@ def lib():
         L.kkm_fit_batched.restype = ctypes.c_int
         L.kkm_fit_batched.argtypes = [ctypes.POINTER(KkmInstance), _i32, _i32, _i32, _i32, _vp,
                                       _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.kkm_warm_start_workspace_bytes.restype = _sz
+        L.kkm_warm_start_workspace_bytes.argtypes = [_i64, _i64, _i64, _i64, _i64, _i32, _i32]
+        L.kkm_warm_start.restype = ctypes.c_int
+        L.kkm_warm_start.argtypes = [_vp, _i64, _i64, _i64, _i64, _vp, _i64, _i64, _i32, _i32,
+                                     _vp, _i32, _i32, _vp, ctypes.POINTER(_d),
+                                     ctypes.POINTER(_i32), ctypes.POINTER(_i32), _vp, _sz, _vp]
         L.kkm_timing_enable.restype = ctypes.c_int
         L.kkm_timing_enable.argtypes = [_i32]
         L.kkm_timing_read.restype = ctypes.c_int
         L.kkm_timing_read.argtypes = [_vp, _vp]
+        L.kkm_timing_spans.restype = ctypes.c_int
+        L.kkm_timing_spans.argtypes = [_i32, _vp, _i64, ctypes.POINTER(_i64)]
         _lib = L
     return _lib
 
@@ -418,6 +430,21 @@ def kkm_timing_read():
             "iterate": (float(ms[2]), int(cnt[2]))}
 
 
+_TIMING_CLASS = {"gram": 0, "sweep": 1, "iterate": 2}
+
+
+def kkm_timing_spans(cls):
+    """Durations in ms (numpy float64, launch order) of the recorded launches of
+    class 'gram', 'sweep' or 'iterate' since timing was enabled."""
+    import numpy as np
+    c = _TIMING_CLASS[cls]
+    cnt = _i64()
+    _check(lib().kkm_timing_spans(c, None, 0, ctypes.byref(cnt)))
+    out = np.zeros(max(int(cnt.value), 1), dtype=np.float64)
+    _check(lib().kkm_timing_spans(c, out.ctypes.data_as(_vp), out.size, ctypes.byref(cnt)))
+    return out[:int(cnt.value)]
+
+
 # ---------------------------------------------------------------- learned warm start
 
 MLP_DIMS = dict(h1=512, h2=512, out=256)
@@ -445,6 +472,22 @@ def kkm_mlp_forward(params, X, h1=512, h2=512, out=256, F=None, ws=None):
     _check(lib().kkm_mlp_forward(_ptr(params), d, h1, h2, out, _ptr(X), n, ldx, _ptr(F), ldf,
                                  _ptr(ws), ws.numel(), _stream()))
     return F
+
+
+def kkm_mlp_forward_layers(params, X, h1=512, h2=512, out=256):
+    """(H1, H2, F): every layer's output of phi_theta(X) on the GPU."""
+    _dev(params, torch.float32, "params", 1)
+    _dev(X, torch.float32, "X", 2)
+    n, d, ldx = _rows(X, "X")
+    if params.numel() != mlp_param_count(d, h1, h2, out):
+        raise ValueError("params has %d entries, expected %d" % (params.numel(),
+                                                                 mlp_param_count(d, h1, h2, out)))
+    H1 = torch.empty((n, h1), dtype=torch.float32, device=X.device)
+    H2 = torch.empty((n, h2), dtype=torch.float32, device=X.device)
+    F = torch.empty((n, out), dtype=torch.float32, device=X.device)
+    _check(lib().kkm_mlp_forward_layers(_ptr(params), d, h1, h2, out, _ptr(X), n, ldx, _ptr(H1),
+                                        _ptr(H2), _ptr(F), out, _stream()))
+    return H1, H2, F
 
 
 def kkm_mlp_loss_grad(params, XB, KB, h1=512, h2=512, out=256, grad=None, ws=None):
@@ -554,3 +597,34 @@ def kkm_feature_kmeanspp(F, k, uniforms, seeds=None, labels_out=None, ws=None):
     _check(lib().kkm_feature_kmeanspp(_ptr(F), n, f, ldf, k, u.ctypes.data_as(_vp), _ptr(seeds),
                                       _ptr(labels_out), _ptr(ws), ws.numel(), _stream()))
     return seeds, labels_out
+
+
+def kkm_warm_start(params, X, k, uniforms, max_iter=60, streams=4, h1=512, h2=512, out=256,
+                   labels_out=None, ws=None):
+    """The learned warm start: phi_theta(X), len(uniforms) k-means++ seedings with
+    Lloyd in feature space, the lowest feature-space objective kept.  uniforms:
+    host float64 [restarts, k] in [0, 1).  Returns a dict with labels (device
+    int32 [n]), objective, cheap_iters (summed over restarts) and best (restart)."""
+    import numpy as np
+    _dev(params, torch.float32, "params", 1)
+    _dev(X, torch.float32, "X", 2)
+    n, d, ldx = _rows(X, "X")
+    if params.numel() != mlp_param_count(d, h1, h2, out):
+        raise ValueError("params has %d entries, expected %d" % (params.numel(),
+                                                                 mlp_param_count(d, h1, h2, out)))
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    if u.ndim != 2 or u.shape[1] != k:
+        raise ValueError("uniforms must be [restarts, k]")
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=X.device)
+    _dev(labels_out, torch.int32, "labels_out", 1)
+    need = int(lib().kkm_warm_start_workspace_bytes(n, d, h1, h2, out, k, streams))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    obj, it, best = _d(), _i32(), _i32()
+    _check(lib().kkm_warm_start(_ptr(params), d, h1, h2, out, _ptr(X), n, ldx, k, u.shape[0],
+                                u.ctypes.data_as(_vp), max_iter, streams, _ptr(labels_out),
+                                ctypes.byref(obj), ctypes.byref(it), ctypes.byref(best), _ptr(ws),
+                                ws.numel(), _stream()))
+    return dict(labels=labels_out, objective=obj.value, cheap_iters=int(it.value),
+                best=int(best.value))

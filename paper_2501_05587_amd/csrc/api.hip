@@ -38,9 +38,8 @@ kkm_status iterate_launch(const void *K, int32_t k_store, int64_t ldk, const flo
 namespace {
 struct TimingState {
     bool on = false;
-    std::vector<TimedSpan> spans;
-    double total_ms[TK_COUNT] = {0, 0, 0};
-    int64_t count[TK_COUNT] = {0, 0, 0};
+    std::vector<TimedSpan> spans;           // recorded, not yet read
+    std::vector<double> done[TK_COUNT];     // durations read, in launch order
 };
 TimingState &timing() {
     static TimingState st;
@@ -145,6 +144,24 @@ using namespace kkm;
 
 extern "C" const char *kkm_last_error(void) { return g_err; }
 
+namespace kkm {
+namespace {
+// Turns every recorded span into a duration (waits for its events).
+kkm_status timing_drain(TimingState &st) {
+    for (auto &sp : st.spans) {
+        float ms = 0.f;
+        KKM_HIP(hipEventSynchronize(sp.stop));
+        KKM_HIP(hipEventElapsedTime(&ms, sp.start, sp.stop));
+        st.done[sp.cls].push_back(ms);
+        (void)hipEventDestroy(sp.start);
+        (void)hipEventDestroy(sp.stop);
+    }
+    st.spans.clear();
+    return KKM_OK;
+}
+}  // namespace
+}  // namespace kkm
+
 extern "C" kkm_status kkm_timing_enable(int32_t on) {
     std::lock_guard<std::mutex> g(g_timing_mu);
     TimingState &st = timing();
@@ -153,10 +170,7 @@ extern "C" kkm_status kkm_timing_enable(int32_t on) {
         (void)hipEventDestroy(sp.stop);
     }
     st.spans.clear();
-    for (int c = 0; c < TK_COUNT; ++c) {
-        st.total_ms[c] = 0.0;
-        st.count[c] = 0;
-    }
+    for (int c = 0; c < TK_COUNT; ++c) st.done[c].clear();
     st.on = on != 0;
     return KKM_OK;
 }
@@ -168,20 +182,27 @@ extern "C" kkm_status kkm_timing_read(double *total_ms, int64_t *launches) {
     }
     std::lock_guard<std::mutex> g(g_timing_mu);
     TimingState &st = timing();
-    for (auto &sp : st.spans) {
-        float ms = 0.f;
-        KKM_HIP(hipEventSynchronize(sp.stop));
-        KKM_HIP(hipEventElapsedTime(&ms, sp.start, sp.stop));
-        st.total_ms[sp.cls] += ms;
-        st.count[sp.cls] += 1;
-        (void)hipEventDestroy(sp.start);
-        (void)hipEventDestroy(sp.stop);
-    }
-    st.spans.clear();
+    KKM_TRY(timing_drain(st));
     for (int c = 0; c < TK_COUNT; ++c) {
-        total_ms[c] = st.total_ms[c];
-        launches[c] = st.count[c];
+        double t = 0.0;
+        for (double v : st.done[c]) t += v;
+        total_ms[c] = t;
+        launches[c] = (int64_t)st.done[c].size();
     }
+    return KKM_OK;
+}
+
+extern "C" kkm_status kkm_timing_spans(int32_t cls, double *ms, int64_t cap, int64_t *count) {
+    if (cls < 0 || cls >= TK_COUNT || !count || (cap > 0 && !ms) || cap < 0) {
+        set_error("kkm_timing_spans: bad class, capacity or NULL output");
+        return KKM_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> g(g_timing_mu);
+    TimingState &st = timing();
+    KKM_TRY(timing_drain(st));
+    const std::vector<double> &v = st.done[cls];
+    *count = (int64_t)v.size();
+    for (int64_t i = 0; i < cap && i < (int64_t)v.size(); ++i) ms[i] = v[(size_t)i];
     return KKM_OK;
 }
 

@@ -250,6 +250,19 @@ extern "C" kkm_status kkm_mlp_forward(const float *params, int64_t d, int64_t h1
     return KKM_OK;
 }
 
+extern "C" kkm_status kkm_mlp_forward_layers(const float *params, int64_t d, int64_t h1,
+                                             int64_t h2, int64_t out, const float *X, int64_t n,
+                                             int64_t ldx, float *H1, float *H2, float *F,
+                                             int64_t ldf, void *stream) {
+    const Dims m{d, h1, h2, out};
+    KKM_TRY(check_dims(m));
+    if (n < 1 || ldx < d || ldf < out || !params || !X || !H1 || !H2 || !F) {
+        set_error("kkm_mlp_forward_layers: bad sizes or NULL pointer");
+        return KKM_ERR_ARG;
+    }
+    return forward_rows(params, m, X, ldx, n, nullptr, H1, nullptr, H2, F, ldf, (hipStream_t)stream);
+}
+
 extern "C" size_t kkm_mlp_train_workspace_bytes(int64_t B, int64_t d, int64_t h1, int64_t h2,
                                                 int64_t out) {
     const Dims m{d, h1, h2, out};
@@ -370,10 +383,7 @@ extern "C" kkm_status kkm_mlp_train_fresh(float *params, float *adam_m, float *a
         set_error("kkm_mlp_train_fresh: bad sizes or NULL pointer");
         return KKM_ERR_ARG;
     }
-    if (kernel_type != KKM_LINEAR && kernel_type != KKM_POLY && kernel_type != KKM_GAUSS) {
-        set_error("kkm_mlp_train_fresh: unknown kernel type %d", kernel_type);
-        return KKM_ERR_ARG;
-    }
+    KKM_TRY(check_kernel(kernel_type, gamma, coef0, degree));
     size_t need = 0;
     TrainWs w = carve_train(ws, m, B, &need);
     const size_t gws = gram_workspace_bytes(B, d, KKM_F32);

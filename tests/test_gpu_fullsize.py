@@ -222,5 +222,28 @@ def test_batched_512_full_size(kkm):
     agree = (tuned["labels"] == base["labels"]).float().mean().item()
     assert agree >= 0.999, agree
     np.testing.assert_allclose(tuned["objective"], base["objective"], rtol=1e-4)
+    # the timed configuration (BF16 product, FP32 K, tuned chunk heights, the
+    # captured graph) against the FP64 oracle on the points the product
+    # multiplies (bfloat16-rounded): the smallest problem of each d and the
+    # smallest overall, whole runs of 30 steps
+    from quantref import bf16_round
+    lab_t = tuned["labels"].cpu().numpy()
+    order = np.argsort(nn)
+    sub = sorted({int(order[0])} | {int(next(b for b in order if specs[b]["d"] == dd))
+                                     for dd in (32, 64, 128, 256)})
+    for b in sub:
+        sp = specs[b]
+        say("  oracle run of problem", b, "n=%d d=%d k=%d" % (sp["n"], sp["d"], sp["k"]))
+        X, _ = datagen.gmm(sp["n"], sp["d"], sp["k"], sp["sigma"], sp["seed"])
+        K_or = oracle.kernel_matrix(bf16_round(X), oracle.GAUSS, sp["gamma"])
+        lab0 = labs[b]
+        ref = oracle.fit(K_or, sp["k"], lab0, 30, check_convergence=False)
+        recs = oracle.trajectory(K_or, sp["k"], lab0, 30, check_convergence=False)
+        tie = any((st["gap"] < 1e-6 * 4).any() for _, st in recs)
+        if not tie:
+            np.testing.assert_array_equal(lab_t[off[b]:off[b + 1]], ref["labels"], err_msg="problem %d" % b)
+        scale = np.abs(np.diag(K_or)).sum() + np.abs(K_or).max() * sp["n"]
+        assert abs(tuned["objective"][b] - ref["objective"]) <= 1e-5 * scale, b
+        assert oracle.adjusted_rand_index(lab_t[off[b]:off[b + 1]], ref["labels"]) >= 0.99, b
     del probs
     torch.cuda.empty_cache()

@@ -36,11 +36,11 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def gram_case(kkm, X, kernel, gamma, coef0, degree, what):
+def gram_case(kkm, X, kernel, gamma, coef0, degree, what, shape=0):
     import torch
-    say("gram", what, X.shape, kernel)
+    say("gram", what, X.shape, kernel, "shape", shape)
     Xd = to_dev(X)
-    K, diag = kkm.kkm_gram(Xd, kernel, gamma, coef0, degree)
+    K, diag = kkm.kkm_gram(Xd, kernel, gamma, coef0, degree, shape=shape)
     torch.cuda.synchronize()
     Kg = K.cpu().numpy().astype(np.float64)
     dg = diag.cpu().numpy()
@@ -78,13 +78,18 @@ def run_teacher_forced(kkm, K, diag, K_or, k, labels0, steps, empty_policy=0, wh
 @pytest.mark.parametrize("n,d", [(1, 1), (7, 3), (63, 5), (65, 16), (129, 33), (300, 2),
                                  (1000, 16), (1100, 64)])
 @pytest.mark.parametrize("kernel", ["linear", "poly", "gauss"])
-def test_gram_parity_shapes(kkm, n, d, kernel):
+@pytest.mark.parametrize("tiles", ["triangle", "full"])
+def test_gram_parity_shapes(kkm, n, d, kernel, tiles):
+    """Both tile shapes of the product (the SYRK triangle with mirrored stores,
+    and the GEMM square where every tile stores its own block) against the
+    oracle's K from the definition."""
     rng = np.random.default_rng(n * 131 + d)
     X = rng.normal(0, 1, (n, d)).astype(np.float32)
     code = {"linear": kkm.LINEAR, "poly": kkm.POLY, "gauss": kkm.GAUSS}[kernel]
     gamma = 1.0 / d if kernel != "linear" else 1.0
+    shape = kkm.GRAM_TRIANGLE if tiles == "triangle" else kkm.GRAM_FULL
     gram_case(kkm, X, code, gamma, 1.0 if kernel == "poly" else 0.0, 2 if kernel == "poly" else 1,
-              "n=%d d=%d %s" % (n, d, kernel))
+              "n=%d d=%d %s" % (n, d, kernel), shape=shape)
 
 
 def test_gram_parity_strided_rows(kkm):
