@@ -202,33 +202,58 @@ def test_mlp_train_steps_match_oracle(kkm):
 
 @pytest.mark.parametrize("d", [D, 1024])
 def test_mlp_train_fresh_steps_match_oracle(kkm, d):
-    """The trainer the benchmark uses: each step's kernel values come from the
-    Gram kernel (FP32) on a fresh batch, then loss, gradient and Adam.  The
-    oracle takes the kernel values from the definition (FP64) on the same rows."""
+    """The trainer the benchmark uses, teacher-forced step by step: each step
+    starts from the oracle's parameters and Adam moments (rounded to FP32), takes
+    its kernel values from the Gram kernel (FP32) on a fresh batch, then loss,
+    gradient and Adam; the oracle takes the kernel values from the definition
+    (FP64) on the same rows.  The step's gradient is read back from the first
+    Adam moment, m' = beta1 m + (1 - beta1) g, and held per parameter block to
+    1e-3 of the block's norm, or to three times the change of the oracle's own
+    gradient under an FP32-rounding perturbation of the parameters where that
+    is larger; the new parameters and moments must be Adam applied to that
+    gradient (FP32 rounding only).  A free-running
+    comparison over several steps is not a property of the arithmetic: Adam's
+    first steps move a parameter by about lr times the sign of its gradient,
+    so a gradient within rounding of zero may move either way."""
     import torch
-    B, steps = 64, 3
+    B, steps, lr, b1 = 64, 3, 1e-3, 0.9
     rng = np.random.default_rng(13 + d)
     Xt = rng.normal(0, 1, (B * steps, d)).astype(np.float32)
-    th = params(4, d)
-    pd = to_dev(th)
-    md = torch.zeros_like(pd)
-    vd = torch.zeros_like(pd)
-    say("mlp train fresh", d)
-    losses = kkm.kkm_mlp_train_fresh(pd, md, vd, to_dev(Xt), B, kkm.GAUSS, 1.0 / d, lr=1e-3)
-    torch.cuda.synchronize()
-    t = th.astype(np.float64)
+    t = params(4, d).astype(np.float64)
     mo = np.zeros_like(t)
     vo = np.zeros_like(t)
+    say("mlp train fresh", d)
     for s_ in range(steps):
+        t, mo, vo = (a.astype(np.float32).astype(np.float64) for a in (t, mo, vo))
+        pd, md, vd = to_dev(t.astype(np.float32)), to_dev(mo.astype(np.float32)), to_dev(vo.astype(np.float32))
         XB = Xt[s_ * B:(s_ + 1) * B]
+        loss = kkm.kkm_mlp_train_fresh(pd, md, vd, to_dev(XB), B, kkm.GAUSS, 1.0 / d, t0=s_, lr=lr)
+        torch.cuda.synchronize()
         KB = oracle.kernel_matrix(XB, oracle.GAUSS, 1.0 / d)
         L, g = omlp.loss_and_grad(t, XB, KB, d, H1, H2, OUT, bf16_operands=True)
-        assert float(losses[s_].item()) == pytest.approx(L, rel=2e-3), s_
-        t, mo, vo = omlp.adam_step(t, mo, vo, g, s_ + 1, lr=1e-3)
-    moved = np.abs(t - th)
-    diff = np.abs(pd.cpu().numpy() - t)
-    assert np.median(diff) <= 0.05 * np.median(moved)
-    assert diff.max() <= 2.5 * 1e-3
+        assert float(loss[0].item()) == pytest.approx(L, rel=1e-4), s_
+        # how far the oracle's own gradient moves when its parameters move by
+        # FP32 rounding (2^-24 relative): activations next to a bfloat16
+        # rounding midpoint then round to the other neighbour, and the
+        # first layer's gradient, a sum with heavy cancellation over the batch,
+        # carries that at about 1e-3 of its norm
+        tp = t * (1 + np.random.default_rng(s_).normal(0, 2.0 ** -24, t.shape))
+        _, gp = omlp.loss_and_grad(tp, XB, KB, d, H1, H2, OUT, bf16_operands=True)
+        m_gpu = md.cpu().numpy().astype(np.float64)
+        g_gpu = (m_gpu - np.float64(np.float32(b1)) * mo) / np.float64(np.float32(1 - b1))
+        off = 0
+        for shape in omlp.param_shapes(d, H1, H2, OUT):
+            size = int(np.prod(shape))
+            a, b, c = g_gpu[off:off + size], g[off:off + size], gp[off:off + size]
+            nb = np.linalg.norm(b)
+            bar = max(1e-3, 3.0 * np.linalg.norm(c - b) / nb)
+            say("  step %d %s: |dg|/|g| %.3g, bar %.3g" % (s_, shape, np.linalg.norm(a - b) / nb, bar))
+            assert np.linalg.norm(a - b) <= bar * nb + 1e-12, (s_, shape)
+            off += size
+        pr, mr, vr = omlp.adam_step(t, mo, vo, g_gpu, s_ + 1, lr=lr)
+        np.testing.assert_allclose(pd.cpu().numpy(), pr, rtol=0, atol=1e-6)
+        np.testing.assert_allclose(vd.cpu().numpy(), vr, rtol=1e-5, atol=1e-12)
+        t, mo, vo = omlp.adam_step(t, mo, vo, g, s_ + 1, lr=lr)
 
 
 def test_mlp_train_fresh_rejects_bad_kernel(kkm):
