@@ -154,6 +154,31 @@ kkm_status kkm_iterate(const void *K, int32_t k_store, int64_t ldk, const float 
 size_t kkm_iterate_workspace_bytes(int64_t n, int32_t k);
 
 /*
+ * kkm_iterate_noalloc — kkm_iterate for callers that cannot allocate device
+ * memory (code under HIP stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same step, the same kernels and bitwise the same
+ * outputs, with no workspace argument.  Its scratch is a file-scope device
+ * array of KKM_NOALLOC_SCRATCH_BYTES (96 MiB: enough for n = 200000 at
+ * k = 64) that each GPU the library runs on holds from the first call on that
+ * device until the process ends; the call itself allocates nothing.
+ *
+ *   Arguments as kkm_iterate without ws / ws_bytes.  The stream (NULL for
+ *   the default stream) must belong to the current device.
+ *   KKM_ERR_UNSUPPORTED when kkm_iterate_workspace_bytes(n, k) exceeds
+ *   KKM_NOALLOC_SCRATCH_BYTES (call kkm_iterate with a workspace instead).
+ *   All calls on one GPU share its array, which keeps the last call's
+ *   contents: calls that overlap on one GPU (two streams or host threads)
+ *   race and must be serialised by the caller.
+ */
+#define KKM_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+kkm_status kkm_iterate_noalloc(const void *K, int32_t k_store, int64_t ldk, const float *diagK,
+                               int64_t n, int32_t k, const int32_t *labels_in,
+                               int32_t empty_policy, int32_t *labels_out, int32_t *counts_out,
+                               int64_t *n_changed, double *J_in, float *D_out, float *ctilde_out,
+                               void *stream);
+size_t kkm_iterate_noalloc_max_bytes(void);
+
+/*
  * kkm_fit — the whole method (Algorithm 2): K once, then steps until no label
  * changes (check_convergence != 0) or max_iter steps ran.
  *

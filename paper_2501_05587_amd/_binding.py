@@ -23,6 +23,7 @@ _STATUS = {0: "KKM_OK", -1: "KKM_ERR_ARG", -2: "KKM_ERR_LABEL", -3: "KKM_ERR_NOM
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkkm.so")
 
 EXPORTS = ("kkm_gram", "kkm_gram_ex", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_workspace_bytes",
+           "kkm_iterate_noalloc", "kkm_iterate_noalloc_max_bytes",
            "kkm_fit", "kkm_fit_ex", "kkm_mlp_param_count", "kkm_mlp_forward",
            "kkm_mlp_forward_workspace_bytes", "kkm_mlp_loss_grad", "kkm_mlp_train_workspace_bytes",
            "kkm_mlp_adam", "kkm_mlp_train", "kkm_feature_lloyd", "kkm_feature_lloyd_workspace_bytes",
@@ -73,6 +74,11 @@ def lib():
         L.kkm_iterate.restype = ctypes.c_int
         L.kkm_iterate.argtypes = [_vp, _i32, _i64, _vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp,
                                   _vp, _vp, _vp, _sz, _vp]
+        L.kkm_iterate_noalloc.restype = ctypes.c_int
+        L.kkm_iterate_noalloc.argtypes = [_vp, _i32, _i64, _vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp,
+                                          _vp, _vp, _vp, _vp]
+        L.kkm_iterate_noalloc_max_bytes.restype = _sz
+        L.kkm_iterate_noalloc_max_bytes.argtypes = []
         L.kkm_fit.restype = ctypes.c_int
         L.kkm_fit.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _d, _d, _i32, _vp, _i32, _i32,
                               _vp, ctypes.POINTER(_d), ctypes.POINTER(_i32), _vp, _i64, _vp]
@@ -224,10 +230,9 @@ def kkm_gram(X, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram_prec=F32, k_s
     return K, diagK
 
 
-def kkm_iterate(K, diagK, labels_in, k, empty_policy=EMPTY_INF, labels_out=None, counts_out=None,
-                n_changed=None, J_in=None, D_out=None, ctilde_out=None, ws=None, k_store=None):
-    """One reassignment step.  Returns (labels_out, counts_out, n_changed[1] int64, J_in[1] f64);
-    D_out / ctilde_out are filled when passed (True allocates them)."""
+def _iterate_outputs(K, diagK, labels_in, k, k_store, labels_out, counts_out, n_changed, J_in, D_out,
+                     ctilde_out):
+    """Checks the step's arguments and allocates the outputs not passed in."""
     if k_store is None:
         k_store = BF16 if K.dtype == torch.bfloat16 else F32
     _dev(K, _kstore_dtype(k_store), "K", 2)
@@ -256,14 +261,41 @@ def kkm_iterate(K, diagK, labels_in, k, empty_policy=EMPTY_INF, labels_out=None,
             raise ValueError("D_out must be contiguous [n, k]")
     if ctilde_out is not None:
         _dev(ctilde_out, torch.float32, "ctilde_out", 1)
+    return k_store, n, ldk, labels_out, counts_out, n_changed, J_in, D_out, ctilde_out
+
+
+def kkm_iterate(K, diagK, labels_in, k, empty_policy=EMPTY_INF, labels_out=None, counts_out=None,
+                n_changed=None, J_in=None, D_out=None, ctilde_out=None, ws=None, k_store=None):
+    """One reassignment step.  Returns (labels_out, counts_out, n_changed[1] int64, J_in[1] f64);
+    D_out / ctilde_out are filled when passed (True allocates them)."""
+    k_store, n, ldk, labels_out, counts_out, n_changed, J_in, D_out, ctilde_out = _iterate_outputs(
+        K, diagK, labels_in, k, k_store, labels_out, counts_out, n_changed, J_in, D_out, ctilde_out)
     need = iterate_workspace_bytes(n, k)
     if ws is None:
-        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=K.device)
     _check(lib().kkm_iterate(_ptr(K), k_store, ldk, _ptr(diagK), n, k, _ptr(labels_in),
                              empty_policy, _ptr(labels_out), _ptr(counts_out), _ptr(n_changed),
                              _ptr(J_in), _ptr(D_out), _ptr(ctilde_out), _ptr(ws), ws.numel(),
                              _stream()))
     return labels_out, counts_out, n_changed, J_in, D_out, ctilde_out
+
+
+def kkm_iterate_noalloc(K, diagK, labels_in, k, empty_policy=EMPTY_INF, labels_out=None,
+                        counts_out=None, n_changed=None, J_in=None, D_out=None, ctilde_out=None,
+                        k_store=None):
+    """kkm_iterate on the library's per-device scratch array (no workspace, no
+    allocation inside the library; outputs not passed in are allocated here)."""
+    k_store, n, ldk, labels_out, counts_out, n_changed, J_in, D_out, ctilde_out = _iterate_outputs(
+        K, diagK, labels_in, k, k_store, labels_out, counts_out, n_changed, J_in, D_out, ctilde_out)
+    _check(lib().kkm_iterate_noalloc(_ptr(K), k_store, ldk, _ptr(diagK), n, k, _ptr(labels_in),
+                                     empty_policy, _ptr(labels_out), _ptr(counts_out),
+                                     _ptr(n_changed), _ptr(J_in), _ptr(D_out), _ptr(ctilde_out),
+                                     _stream()))
+    return labels_out, counts_out, n_changed, J_in, D_out, ctilde_out
+
+
+def iterate_noalloc_max_bytes() -> int:
+    return int(lib().kkm_iterate_noalloc_max_bytes())
 
 
 def kkm_fit(X, k, labels0, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, max_iter=30,
