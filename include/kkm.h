@@ -457,6 +457,49 @@ size_t kkm_warm_start_workspace_bytes(int64_t n, int64_t d, int64_t h1, int64_t 
                                       int32_t k, int32_t streams);
 
 /*
+ * kkm_iterate_matfree — one reassignment step without a stored kernel matrix
+ * (the paper computes K once, Sec. 3.2, and streams it every iteration,
+ * Sec. 4.3; here every entry K_ij = kappa(x_i, x_j) is recomputed on the
+ * MFMA inside the step and added into E = K V^T at once, Eq. dist_sp_1, so
+ * no n x n buffer exists).  Worth it below the product's ridge point (small
+ * d); the result is the stored-K step's up to summation order.
+ *
+ *   X, n, d, ldx, kernel_type, gamma, coef0, degree, gram_prec   as kkm_gram
+ *              (the product in FP32, BF16 or FP8 per-row scaled; the kernel
+ *              values summed are not rounded further, as k_store = KKM_F32).
+ *   k, labels_in, empty_policy, labels_out, counts_out, n_changed, J_in,
+ *   D_out, ctilde_out   as kkm_iterate.
+ *   diagK_out  [n] float32, nullable: K_ii as the step used it.
+ *   ws, ws_bytes  device workspace of at least
+ *              kkm_iterate_matfree_workspace_bytes(n, d, k, gram_prec).
+ * Asynchronous; deterministic.  Errors as kkm_gram and kkm_iterate.
+ */
+kkm_status kkm_iterate_matfree(const float *X, int64_t n, int64_t d, int64_t ldx,
+                               int32_t kernel_type, double gamma, double coef0, int32_t degree,
+                               int32_t gram_prec, int32_t k, const int32_t *labels_in,
+                               int32_t empty_policy, int32_t *labels_out, int32_t *counts_out,
+                               int64_t *n_changed, double *J_in, float *D_out, float *ctilde_out,
+                               float *diagK_out, void *ws, size_t ws_bytes, void *stream);
+size_t kkm_iterate_matfree_workspace_bytes(int64_t n, int64_t d, int32_t k, int32_t gram_prec);
+
+/*
+ * kkm_fit_matfree — Algorithm 2 end to end with the matrix-free step: the
+ * product's inputs (rounded rows, squared norms) and diag(K) once, then
+ * kkm_iterate_matfree steps until no label changes (check_convergence != 0)
+ * or max_iter steps, then the objective of the final labels.  Arguments and
+ * results as kkm_fit_ex without K (k_store is FP32 by construction);
+ * times_ms (host double [3], nullable): {prologue, all steps, final
+ * objective}.  Allocates its workspace (about (slots + d) n floats, no n^2
+ * term) and synchronises the stream before returning.
+ */
+kkm_status kkm_fit_matfree(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t k,
+                           int32_t kernel_type, double gamma, double coef0, int32_t degree,
+                           int32_t gram_prec, int32_t empty_policy, const int32_t *labels0,
+                           int32_t max_iter, int32_t check_convergence, int32_t *labels_out,
+                           double *objective, int32_t *iters, double *J_trace,
+                           int64_t *changed_trace, double *times_ms, void *stream);
+
+/*
  * Launch timing for benchmarks (process-wide).  kkm_timing_enable(1) clears
  * the records and starts bracketing every Gram launch, every SpMM sweep launch
  * and every whole kkm_iterate step with HIP events on the caller's stream;

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkkm.so")
 
 EXPORTS = ("kkm_gram", "kkm_gram_ex", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_workspace_bytes",
            "kkm_iterate_noalloc", "kkm_iterate_noalloc_max_bytes",
+           "kkm_iterate_matfree", "kkm_iterate_matfree_workspace_bytes", "kkm_fit_matfree",
            "kkm_fit", "kkm_fit_ex", "kkm_mlp_param_count", "kkm_mlp_forward",
            "kkm_mlp_forward_workspace_bytes", "kkm_mlp_loss_grad", "kkm_mlp_train_workspace_bytes",
            "kkm_mlp_adam", "kkm_mlp_train", "kkm_feature_lloyd", "kkm_feature_lloyd_workspace_bytes",
@@ -79,6 +80,15 @@ def lib():
                                           _vp, _vp, _vp, _vp]
         L.kkm_iterate_noalloc_max_bytes.restype = _sz
         L.kkm_iterate_noalloc_max_bytes.argtypes = []
+        L.kkm_iterate_matfree_workspace_bytes.restype = _sz
+        L.kkm_iterate_matfree_workspace_bytes.argtypes = [_i64, _i64, _i32, _i32]
+        L.kkm_iterate_matfree.restype = ctypes.c_int
+        L.kkm_iterate_matfree.argtypes = [_vp, _i64, _i64, _i64, _i32, _d, _d, _i32, _i32, _i32, _vp,
+                                          _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.kkm_fit_matfree.restype = ctypes.c_int
+        L.kkm_fit_matfree.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _d, _d, _i32, _i32, _i32,
+                                      _vp, _i32, _i32, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i32),
+                                      _vp, _vp, _vp, _vp]
         L.kkm_fit.restype = ctypes.c_int
         L.kkm_fit.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _d, _d, _i32, _vp, _i32, _i32,
                               _vp, ctypes.POINTER(_d), ctypes.POINTER(_i32), _vp, _i64, _vp]
@@ -335,6 +345,85 @@ def kkm_fit_ex(X, k, labels0, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram
                             ctypes.byref(it), _ptr(K_ws), ldk,
                             Jt.ctypes.data_as(_vp), Ct.ctypes.data_as(_vp), tm.ctypes.data_as(_vp),
                             _stream()))
+    t = int(it.value)
+    return dict(labels=labels_out, objective=J.value, iters=t, J_trace=Jt[:t + 1],
+                changed_trace=Ct[:t], times_ms=tm)
+
+
+def matfree_workspace_bytes(n: int, d: int, k: int, gram_prec: int = F32) -> int:
+    return int(lib().kkm_iterate_matfree_workspace_bytes(n, d, k, gram_prec))
+
+
+def kkm_iterate_matfree(X, labels_in, k, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1,
+                        gram_prec=F32, empty_policy=EMPTY_INF, labels_out=None, counts_out=None,
+                        n_changed=None, J_in=None, D_out=None, ctilde_out=None, diagK_out=None,
+                        ws=None):
+    """One reassignment step that recomputes the kernel values instead of
+    reading a stored K.  Returns (labels_out, counts_out, n_changed, J_in,
+    D_out, ctilde_out, diagK_out); D_out / ctilde_out / diagK_out are filled
+    when passed (True allocates them)."""
+    _dev(X, torch.float32, "X", 2)
+    n, d, ldx = _rows(X, "X")
+    _dev(labels_in, torch.int32, "labels_in", 1)
+    dev = X.device
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=dev)
+    if counts_out is None:
+        counts_out = torch.empty(k, dtype=torch.int32, device=dev)
+    if n_changed is None:
+        n_changed = torch.empty(1, dtype=torch.int64, device=dev)
+    if J_in is None:
+        J_in = torch.empty(1, dtype=torch.float64, device=dev)
+    if D_out is True:
+        D_out = torch.empty((n, k), dtype=torch.float32, device=dev)
+    if ctilde_out is True:
+        ctilde_out = torch.empty(k, dtype=torch.float32, device=dev)
+    if diagK_out is True:
+        diagK_out = torch.empty(n, dtype=torch.float32, device=dev)
+    for t, dt, nm in ((labels_out, torch.int32, "labels_out"), (counts_out, torch.int32, "counts_out"),
+                      (n_changed, torch.int64, "n_changed"), (J_in, torch.float64, "J_in")):
+        _dev(t, dt, nm)
+    if D_out is not None:
+        _dev(D_out, torch.float32, "D_out", 2)
+        if not D_out.is_contiguous() or tuple(D_out.shape) != (n, k):
+            raise ValueError("D_out must be contiguous [n, k]")
+    if ctilde_out is not None:
+        _dev(ctilde_out, torch.float32, "ctilde_out", 1)
+    if diagK_out is not None:
+        _dev(diagK_out, torch.float32, "diagK_out", 1)
+    need = matfree_workspace_bytes(n, d, k, gram_prec)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib().kkm_iterate_matfree(_ptr(X), n, d, ldx, kernel, gamma, coef0, degree, gram_prec, k,
+                                     _ptr(labels_in), empty_policy, _ptr(labels_out),
+                                     _ptr(counts_out), _ptr(n_changed), _ptr(J_in), _ptr(D_out),
+                                     _ptr(ctilde_out), _ptr(diagK_out), _ptr(ws), ws.numel(),
+                                     _stream()))
+    return labels_out, counts_out, n_changed, J_in, D_out, ctilde_out, diagK_out
+
+
+def kkm_fit_matfree(X, k, labels0, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram_prec=F32,
+                    empty_policy=EMPTY_INF, max_iter=30, check_convergence=True, labels_out=None):
+    """The whole method with the matrix-free step (no n x n buffer).  Returns a
+    dict with labels, objective, iters, J_trace, changed_trace and times_ms
+    (prologue, steps, final J)."""
+    import numpy as np
+
+    _dev(X, torch.float32, "X", 2)
+    n, d, ldx = _rows(X, "X")
+    _dev(labels0, torch.int32, "labels0", 1)
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=X.device)
+    J = _d()
+    it = _i32()
+    Jt = np.zeros(max_iter + 1, dtype=np.float64)
+    Ct = np.zeros(max(max_iter, 1), dtype=np.int64)
+    tm = np.zeros(3, dtype=np.float64)
+    _check(lib().kkm_fit_matfree(_ptr(X), n, d, ldx, k, kernel, gamma, coef0, degree, gram_prec,
+                                 empty_policy, _ptr(labels0), max_iter, int(bool(check_convergence)),
+                                 _ptr(labels_out), ctypes.byref(J), ctypes.byref(it),
+                                 Jt.ctypes.data_as(_vp), Ct.ctypes.data_as(_vp),
+                                 tm.ctypes.data_as(_vp), _stream()))
     t = int(it.value)
     return dict(labels=labels_out, objective=J.value, iters=t, J_trace=Jt[:t + 1],
                 changed_trace=Ct[:t], times_ms=tm)

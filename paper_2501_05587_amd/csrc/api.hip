@@ -281,19 +281,18 @@ extern "C" kkm_status kkm_iterate(const void *K, int32_t k_store, int64_t ldk,
 }
 
 namespace kkm {
-namespace {
-
-// The loop of Algorithm 2 on a resident K: steps from labels0 until no label
-// changes (check_convergence) or max_iter steps, then the objective of the
-// final labels (free when the last step changed nothing).  times_ms (host
+// The loop of Algorithm 2: steps from labels0 until no label changes
+// (check_convergence) or max_iter steps, then the objective of the final
+// labels (free when the last step changed nothing).  Each step is one call of
+// `step` (labels in, labels out, sizes, changed count and J of the input
+// labels, all device; a workspace of step_ws bytes).  times_ms (host
 // double[2], nullable): {all steps, final objective pass}.
-kkm_status run_loop(const void *K, int32_t k_store, int64_t ldk, const float *diag, int64_t n,
-                    int32_t k, int32_t empty_policy, const int32_t *labels0, int32_t max_iter,
-                    int32_t check_convergence, int32_t *labels_out, double *objective,
-                    int32_t *iters, double *J_trace, int64_t *changed_trace, double *times_ms,
-                    const char *who, hipStream_t s) {
+kkm_status run_steps(const StepFn &step, size_t step_ws, int64_t n, int32_t k,
+                     const int32_t *labels0, int32_t max_iter, int32_t check_convergence,
+                     int32_t *labels_out, double *objective, int32_t *iters, double *J_trace,
+                     int64_t *changed_trace, double *times_ms, const char *who, hipStream_t s) {
     const int32_t steps_cap = max_iter + 1;
-    const size_t iws = iterate_workspace_bytes(n, k);
+    const size_t iws = step_ws;
     FitBuffers fb;
     Carver c(nullptr);
     c.take<char>(iws);
@@ -328,9 +327,7 @@ kkm_status run_loop(const void *K, int32_t k_store, int64_t ldk, const float *di
     int64_t last_changed = -1;
     int64_t *hchanged = reinterpret_cast<int64_t *>(fb.host + 1);
     for (; t < max_iter; ++t) {
-        KKM_TRY(iterate_launch(K, k_store, ldk, diag, n, k, lab[cur], empty_policy, lab[cur ^ 1],
-                               counts, changed_dev + t, J_dev + t, nullptr, nullptr, iter_ws, iws,
-                               s));
+        KKM_TRY(step(lab[cur], lab[cur ^ 1], counts, changed_dev + t, J_dev + t, iter_ws, iws, s));
         if (check_convergence || t == 0) {
             KKM_HIP(hipMemcpyAsync(hchanged, changed_dev + t, sizeof(int64_t),
                                    hipMemcpyDeviceToHost, s));
@@ -350,11 +347,8 @@ kkm_status run_loop(const void *K, int32_t k_store, int64_t ldk, const float *di
     KKM_HIP(hipEventRecord(ev[1], s));
     // objective of the final labels: free after a step that changed nothing
     const bool need_final = !(t > 0 && last_changed == 0);
-    if (need_final) {
-        KKM_TRY(iterate_launch(K, k_store, ldk, diag, n, k, lab[cur], empty_policy, lab[cur ^ 1],
-                               counts, changed_dev + t, J_dev + t, nullptr, nullptr, iter_ws, iws,
-                               s));
-    }
+    if (need_final)
+        KKM_TRY(step(lab[cur], lab[cur ^ 1], counts, changed_dev + t, J_dev + t, iter_ws, iws, s));
     KKM_HIP(hipEventRecord(ev[2], s));
     KKM_HIP(hipMemcpyAsync(labels_out, lab[cur], (size_t)n * sizeof(int32_t),
                            hipMemcpyDeviceToDevice, s));
@@ -394,6 +388,24 @@ kkm_status run_loop(const void *K, int32_t k_store, int64_t ldk, const float *di
     delete[] hc;
     delete[] hj;
     return st;
+}
+
+namespace {
+
+// run_steps with the stored-K step (kkm_iterate's kernels).
+kkm_status run_loop(const void *K, int32_t k_store, int64_t ldk, const float *diag, int64_t n,
+                    int32_t k, int32_t empty_policy, const int32_t *labels0, int32_t max_iter,
+                    int32_t check_convergence, int32_t *labels_out, double *objective,
+                    int32_t *iters, double *J_trace, int64_t *changed_trace, double *times_ms,
+                    const char *who, hipStream_t s) {
+    const StepFn step = [&](const int32_t *in, int32_t *out, int32_t *counts, int64_t *changed,
+                            double *J, void *ws, size_t ws_bytes, hipStream_t st) {
+        return iterate_launch(K, k_store, ldk, diag, n, k, in, empty_policy, out, counts, changed,
+                              J, nullptr, nullptr, ws, ws_bytes, st);
+    };
+    return run_steps(step, iterate_workspace_bytes(n, k), n, k, labels0, max_iter,
+                     check_convergence, labels_out, objective, iters, J_trace, changed_trace,
+                     times_ms, who, s);
 }
 
 }  // namespace

@@ -90,6 +90,13 @@ kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clu
                        int64_t sweep_grid, int32_t max_k, int32_t k_store, bool vec,
                        const int32_t *labels_in, int32_t *labels_out, hipStream_t stream);
 
+// One step of a single problem with the sweep replaced by `sweep` (which must
+// fill in.P and in.Zp as the stored-K sweep does), between the CSR build of V
+// and the centroid norms.
+kkm_status step_launch_custom(const Inst &in, const int32_t *labels_in, int32_t *labels_out,
+                              const std::function<kkm_status(hipStream_t)> &sweep,
+                              hipStream_t stream);
+
 kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,
                       int32_t *blk_bad, int32_t *err, int32_t *counts, int32_t *perm,
                       int32_t *offsets, int32_t *counts_out, int64_t *n_changed,

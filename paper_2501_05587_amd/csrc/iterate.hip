@@ -751,6 +751,44 @@ kkm_status step_launch(const InstSet &s, int64_t total_blocks, int64_t total_clu
                                 labels_in, labels_out, stream);
 }
 
+// One step of a single problem whose sweep is supplied by the caller: the CSR
+// build of V, then `sweep` (it fills in.P and in.Zp as spmm_row_sweep does:
+// slot q + c of P holds, for every column, the sum over the positions of
+// chunk q in cluster c, and Zp[(q + c) nws + w] that slot's own-cluster sum
+// over the w-th strip of in.n / in.nws columns), then the centroid norms, the
+// fused assignment and the objective.
+kkm_status step_launch_custom(const Inst &in, const int32_t *labels_in, int32_t *labels_out,
+                              const std::function<kkm_status(hipStream_t)> &sweep,
+                              hipStream_t stream) {
+    InstSet s{};
+    s.count = 1;
+    s.one = in;
+    const int32_t k = in.k;
+    const dim3 pb(kPtsPerBlock);
+    const TimedSpan whole = timing_begin(TK_ITERATE, stream);
+    hipLaunchKernelGGL(v_block_hist<false>, dim3((unsigned)in.nblk), pb,
+                       (size_t)(k + 1) * sizeof(int32_t), stream, s, labels_in);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(v_cluster_scan<false>, dim3((unsigned)k), dim3(256), 0, stream, s);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(v_scatter<false>, dim3((unsigned)in.nblk), pb,
+                       (size_t)(k + 1 + 4 * k) * sizeof(int32_t), stream, s, labels_in);
+    KKM_HIP(hipGetLastError());
+    const TimedSpan span = timing_begin(TK_SWEEP, stream);
+    KKM_TRY(sweep(stream));
+    timing_end(span, stream);
+    hipLaunchKernelGGL((centroid_norms<4, false>), dim3((unsigned)k), dim3(256), 0, stream, s);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(assign_fused<false>, dim3((unsigned)in.nblk), pb,
+                       (size_t)(2 * k + 1 + kSlotWindow) * sizeof(int32_t), stream, s, labels_in,
+                       labels_out);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(j_finalize<false>, dim3(1u), pb, 0, stream, s);
+    KKM_HIP(hipGetLastError());
+    timing_end(whole, stream);
+    return KKM_OK;
+}
+
 // V in CSR form for one problem (used by the feature-space Lloyd iterations):
 // the first three kernels of a step on a set of one.
 kkm_status vcsr_build(const int32_t *labels, int64_t n, int32_t k, int32_t *blk_hist,

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "../../include/kkm.h"
 
 namespace kkm {
@@ -64,6 +66,21 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
                        double gamma, double coef0, int32_t degree, int32_t gram_prec,
                        int32_t k_store, void *K, int64_t ldk, float *diagK, void *ws,
                        size_t ws_bytes, hipStream_t stream, int32_t shape = KKM_GRAM_TRIANGLE);
+
+// The loop of Algorithm 2 around a step function: steps from labels0 until
+// no label changes (check_convergence != 0) or max_iter steps, then the
+// objective of the final labels; synchronises `s` before returning.  `step`
+// performs one reassignment step (labels in, labels out, cluster sizes,
+// changed count and J of the input labels, all device pointers) on a
+// workspace of step_ws bytes.  times_ms (host double[2], nullable): {all
+// steps, final objective pass}.
+using StepFn = std::function<kkm_status(const int32_t *labels_in, int32_t *labels_out,
+                                        int32_t *counts, int64_t *n_changed, double *J_in,
+                                        void *ws, size_t ws_bytes, hipStream_t s)>;
+kkm_status run_steps(const StepFn &step, size_t step_ws, int64_t n, int32_t k,
+                     const int32_t *labels0, int32_t max_iter, int32_t check_convergence,
+                     int32_t *labels_out, double *objective, int32_t *iters, double *J_trace,
+                     int64_t *changed_trace, double *times_ms, const char *who, hipStream_t s);
 
 // ---------------------------------------------------------------- workspace carving
 
