@@ -29,6 +29,8 @@ Also reported:
   and the rings workload (n=1000): Gram and sweep rooflines, time per step;
 * roofline positions of the sweep (HBM) and the Gram (MFMA) from HIP-event
   timings of those launches, and HBM traffic from the recorded counters;
+* the matrix-free step (no stored K) beside the stored-K step at n=100000,
+  k=32, d in {32, 64, 128, 256}, BF16 product;
 * the FP64 oracle timed on the host on the first 20000 points (K build and
   loop apart, all host threads and one thread, median of 3), beside the GPU
   on the same points.
@@ -36,7 +38,7 @@ Also reported:
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows N]
        [--no-cpu-baseline] [--no-converge] [--no-learned] [--no-batched]
        [--cpu-full] [--copy-calibration] [--gram-shapes] [--learned-only]
-       [--batched-only]
+       [--batched-only] [--matfree-only] [--no-matfree] [--profile-kernels]
 """
 import argparse
 import json
@@ -450,6 +452,195 @@ def rings_leg(kkm, torch, dev, reps=5):
             "us_per_iter": med * 1e3, "seconds_to_converge": secs}
 
 
+def matfree_leg(kkm, torch, dev, iters=30, ds=(32, 64, 128, 256)):
+    """The matrix-free step (kernel values recomputed on the MFMA every step,
+    no stored K) beside the stored-K step, BF16 product, n=100000, k=32: at
+    d=128 on the learned warm-start workload's points, at the other d on a
+    32-component mixture of the same recipe.  Per d: the median time of one
+    step (iterations 2..30 of a fixed 30-iteration run), the matrix-free
+    sweep's flop rate (2 n^2 d per step, the products it recomputes) against
+    the BF16 MFMA peak, and the stored-K sweep's HBM rate (n^2 bfloat16
+    entries read per step); at d=128 also both forms to convergence from the
+    random labels."""
+    import numpy as np
+
+    import datagen
+    w = datagen.WORKLOADS["learned100k"]
+    n, k = w.n, w.k
+    out = {"n": n, "k": k, "gram": "bf16 mfma", "iterations": iters, "by_d": []}
+    for d in ds:
+        if d == w.d:
+            X, _ = w.points()
+            l0 = w.labels0()
+        else:
+            X, _ = datagen.gmm(n, d, k, 0.5, 7000 + d)
+            l0 = datagen.uniform_labels(n, k, 7100 + d)
+        gamma = 1.0 / d
+        Xd = torch.from_numpy(X).to(dev)
+        ld = torch.from_numpy(l0).to(dev)
+        K16 = kkm.alloc_kernel_matrix(n, kkm.BF16, dev)
+        lab = torch.empty(n, dtype=torch.int32, device=dev)
+
+        def stored(max_iter=iters, conv=False):
+            return kkm.kkm_fit_ex(Xd, k, ld, kkm.GAUSS, gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
+                                  max_iter=max_iter, check_convergence=conv, K_ws=K16, labels_out=lab)
+
+        def matfree(max_iter=iters, conv=False):
+            return kkm.kkm_fit_matfree(Xd, k, ld, kkm.GAUSS, gamma, gram_prec=kkm.BF16,
+                                       max_iter=max_iter, check_convergence=conv, labels_out=lab)
+
+        rec = {"d": d}
+        for name, fn in (("stored_k", stored), ("matfree", matfree)):
+            fn(3)
+            torch.cuda.synchronize()
+            kkm.kkm_timing_enable(True)
+            r = fn()
+            torch.cuda.synchronize()
+            its = iter_spans(kkm, 1, iters + 1)
+            sw = float(np.median(kkm.kkm_timing_spans("sweep")))
+            kkm.kkm_timing_enable(False)
+            med = float(np.median(its))
+            rr = {"iter_ms": med, "sweep_ms": sw, "objective_30": r["objective"]}
+            if name == "stored_k":
+                rr["sweep_hbm_gbs"] = float(n) * n * 2 / (sw * 1e-3) / 1e9
+                rr["sweep_frac_hbm"] = rr["sweep_hbm_gbs"] / HBM_PEAK_GBS
+            else:
+                fl = 2.0 * n * n * d
+                rr["sweep_tflops"] = fl / (sw * 1e-3) / 1e12
+                rr["sweep_frac_bf16_mfma"] = rr["sweep_tflops"] / BF16_MFMA_PEAK_TFS
+            rec[name] = rr
+        rec["matfree_over_stored_step_time"] = rec["matfree"]["iter_ms"] / rec["stored_k"]["iter_ms"]
+        if d == w.d:
+            cs, rc = timed_runs(torch, lambda: stored(300, True), reps=2)
+            lc = lab.cpu().numpy()
+            ms, rm = timed_runs(torch, lambda: matfree(300, True), reps=2)
+            lm = lab.cpu().numpy()
+            rec["to_convergence"] = {
+                "stored_k": {"seconds": cs, "iters": rc["iters"], "objective": rc["objective"]},
+                "matfree": {"seconds": ms, "iters": rm["iters"], "objective": rm["objective"]},
+                "ari_matfree_vs_stored": ari(lm, lc)}
+        log("matfree d=%d: step %.3f ms (sweep %.3f ms, %.0f TF/s = %.3f of BF16 MFMA) vs stored-K "
+            "step %.3f ms (sweep %.3f ms, %.3f of HBM)" % (
+                d, rec["matfree"]["iter_ms"], rec["matfree"]["sweep_ms"],
+                rec["matfree"]["sweep_tflops"], rec["matfree"]["sweep_frac_bf16_mfma"],
+                rec["stored_k"]["iter_ms"], rec["stored_k"]["sweep_ms"],
+                rec["stored_k"]["sweep_frac_hbm"]))
+        out["by_d"].append(rec)
+        del K16, Xd
+        torch.cuda.empty_cache()
+    return out
+
+
+def packed_leg(kkm, torch, dev, iters=30, reps=2):
+    """The strip-packed symmetric K (upper triangle in strips, each stored
+    entry read once per step) beside the dense K on the benchmark workload
+    (n=200000, d=1024, k=64): FP32 and bfloat16 storage, 30 fixed iterations
+    from the random labels.  Per form: the median step (iterations 2..30), the
+    packed sweep (both parts and the fold of the row part) against the bytes
+    it must read (the packed entries: about n^2/2 s_K), and the Gram writing
+    the packed K; and to convergence from the random labels (FP32) and from
+    nothing else."""
+    import numpy as np
+
+    import datagen
+    w = datagen.WORKLOADS["gmm200k"]
+    n = w.n
+    X, _ = w.points()
+    Xd = torch.from_numpy(X).to(dev)
+    del X
+    ld = torch.from_numpy(w.labels0()).to(dev)
+    lab = torch.empty(n, dtype=torch.int32, device=dev)
+    out = {"n": n, "d": w.d, "k": w.k, "iterations": iters}
+    for name, ks in (("f32", kkm.F32), ("bf16", kkm.BF16)):
+        Kp = kkm.alloc_packed_kernel_matrix(n, ks, dev)
+        eb = 4 if ks == kkm.F32 else 2
+
+        def run(max_iter=iters, conv=False):
+            return kkm.kkm_fit_packed(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=ks, k_store=ks,
+                                      max_iter=max_iter, check_convergence=conv, K_ws=Kp,
+                                      labels_out=lab)
+
+        run(2)
+        torch.cuda.synchronize()
+        kkm.kkm_timing_enable(True)
+        for _ in range(reps):
+            r = run()
+        torch.cuda.synchronize()
+        its = iter_spans(kkm, reps, iters + 1)
+        sw = float(np.median(kkm.kkm_timing_spans("sweep")))
+        gram = float(np.median(kkm.kkm_timing_spans("gram")))
+        kkm.kkm_timing_enable(False)
+        pbytes = float(kkm.packed_elements(n, ks)) * eb
+        med = float(np.median(its))
+        rec = {"k_store": name, "packed_bytes": pbytes, "dense_bytes": float(n) * n * eb,
+               "iter_ms": med, "iters_per_s": 1e3 / med, "sweep_ms": sw,
+               "sweep_gbs_packed_bytes": pbytes / (sw * 1e-3) / 1e9,
+               "sweep_frac_hbm": pbytes / (sw * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "gram_ms": gram, "objective_30": r["objective"]}
+        if ks == kkm.F32:
+            cs, rc = timed_runs(torch, lambda: run(300, True), reps=1)
+            rec["to_convergence"] = {"seconds": cs, "iters": rc["iters"], "objective": rc["objective"]}
+        log("packed %s: step %.3f ms (%.1f iters/s), sweep %.3f ms = %.0f GB/s on %.1f GB (%.3f of HBM), "
+            "gram %.1f ms" % (name, med, 1e3 / med, sw, rec["sweep_gbs_packed_bytes"], pbytes / 1e9,
+                              rec["sweep_frac_hbm"], gram))
+        out[name] = rec
+        del Kp
+        torch.cuda.empty_cache()
+    return out
+
+
+def profile_kernels(kkm, torch, dev):
+    """One launch of each product kernel at its benchmark size, for counter
+    collection under rocprofv3: the FP32 and the BF16 Gram at n=200000,
+    d=1024 (K stored FP32 / bfloat16) with two steps on each K, the packed
+    Gram and two packed steps for both element types, the BF16 Gram at
+    n=100000, d=128, and two matrix-free steps there (BF16 product)."""
+    import datagen
+    out = {}
+    w = datagen.WORKLOADS["gmm200k"]
+    X, _ = w.points()
+    Xd = torch.from_numpy(X).to(dev)
+    del X
+    ld = torch.from_numpy(w.labels0()).to(dev)
+    for name, gp, ks in (("gram_f32_gmm200k", kkm.F32, kkm.F32), ("gram_bf16_gmm200k", kkm.BF16, kkm.BF16)):
+        K = kkm.alloc_kernel_matrix(w.n, ks, dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        K, dg = kkm.kkm_gram(Xd, w.kernel, w.gamma, gram_prec=gp, k_store=ks, K=K)
+        torch.cuda.synchronize()
+        out[name] = time.perf_counter() - t
+        for _ in range(2):  # two steps of the dense sweep on this K
+            kkm.kkm_iterate(K, dg, ld, w.k)
+        torch.cuda.synchronize()
+        log("profile: %s %.3f s, two steps" % (name, out[name]))
+        del K
+        torch.cuda.empty_cache()
+    for name, ks in (("packed_f32_gmm200k", kkm.F32), ("packed_bf16_gmm200k", kkm.BF16)):
+        Kp, dg = kkm.kkm_gram_packed(Xd, w.kernel, w.gamma, gram_prec=ks, k_store=ks)
+        for _ in range(2):
+            kkm.kkm_iterate_packed(Kp, dg, ld, w.k)
+        torch.cuda.synchronize()
+        log("profile: %s, two steps" % name)
+        del Kp
+        torch.cuda.empty_cache()
+    del Xd
+    w = datagen.WORKLOADS["learned100k"]
+    X, _ = w.points()
+    Xd = torch.from_numpy(X).to(dev)
+    ld = torch.from_numpy(w.labels0()).to(dev)
+    K = kkm.alloc_kernel_matrix(w.n, kkm.BF16, dev)
+    kkm.kkm_gram(Xd, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16, K=K)
+    torch.cuda.synchronize()
+    del K
+    torch.cuda.empty_cache()
+    log("profile: gram_bf16_learned100k done")
+    for _ in range(2):
+        kkm.kkm_iterate_matfree(Xd, ld, w.k, w.kernel, w.gamma, gram_prec=kkm.BF16)
+    torch.cuda.synchronize()
+    log("profile: matfree steps done")
+    return out
+
+
 def error_report(K_or, k, labels_in, orc, D, J):
     """One step's error against the oracle's step from the same labels: the
     largest distance error over the condition scale sigma_i = |K_ii| +
@@ -656,6 +847,13 @@ def main():
                     help="run only the learned warm start on its n=100000, k=32 workload")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched form and print its record")
+    ap.add_argument("--matfree-only", action="store_true",
+                    help="run only the matrix-free step beside the stored-K step (n=100000, k=32)")
+    ap.add_argument("--no-matfree", action="store_true")
+    ap.add_argument("--packed-only", action="store_true",
+                    help="run only the strip-packed K beside the dense K (n=200000, FP32 and BF16)")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="one launch of each product kernel at its benchmark size (for rocprofv3)")
     ap.add_argument("--gram-shapes", action="store_true",
                     help="time the triangle and full tile shapes of the Gram over n and d")
     args = ap.parse_args()
@@ -677,6 +875,15 @@ def main():
         return
     if args.gram_shapes:
         print(json.dumps({"gram_shapes": gram_shapes(kkm, torch, dev)}), flush=True)
+        return
+    if args.matfree_only:
+        print(json.dumps({"matfree": matfree_leg(kkm, torch, dev)}), flush=True)
+        return
+    if args.packed_only:
+        print(json.dumps({"packed": packed_leg(kkm, torch, dev)}), flush=True)
+        return
+    if args.profile_kernels:
+        print(json.dumps({"profile_kernels": profile_kernels(kkm, torch, dev)}), flush=True)
         return
     if args.learned_only:
         print(json.dumps(learned_c5_leg(kkm, torch, dev)), flush=True)
@@ -860,6 +1067,7 @@ def main():
         small = {"mnist_like": mnist_leg(kkm, torch, dev), "rings": rings_leg(kkm, torch, dev)}
     batched = None if args.no_batched else batched_leg(kkm, torch, dev, iters)
     learned_c5 = None if (args.no_learned or args.no_converge) else learned_c5_leg(kkm, torch, dev)
+    matfree = None if args.no_matfree else matfree_leg(kkm, torch, dev)
 
     cpu = None
     same_prefix = None
@@ -902,6 +1110,7 @@ def main():
         "rings_1k": small and small["rings"],
         "batched": batched,
         "learned_warm_start_100k": learned_c5,
+        "matfree_vs_stored_k_100k": matfree,
         "roofline": roof,
         "roofline_gram": roof_g,
         "cpu_baseline": cpu,

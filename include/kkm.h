@@ -500,6 +500,47 @@ kkm_status kkm_fit_matfree(const float *X, int64_t n, int64_t d, int64_t ldx, in
                            int64_t *changed_trace, double *times_ms, void *stream);
 
 /*
+ * The strip-packed symmetric K (Sec. 4.2 names packed triangular storage as
+ * what a SYRK-built K needs; Sec. 4.3 streams K every iteration): the upper
+ * triangle in strips of W columns (W = 1024 for FP32, 2048 for bfloat16).
+ * Row i, in strip s_i = i / W, stores its columns [s_i W, ns W) contiguously,
+ * ns = ceil(n / W): the diagonal W x W block of each strip whole, every block
+ * right of it once, about n^2 / 2 entries.  Rows follow each other with no
+ * stride argument; kkm_packed_elements(n, k_store) entries in all.
+ *
+ * kkm_gram_packed — kkm_gram writing K in this layout (the 128 x 128
+ * triangle of tiles; K 16-byte aligned).  Arguments as kkm_gram without ldk.
+ *
+ * kkm_iterate_packed — kkm_iterate on a strip-packed K: each stored entry is
+ * read once and feeds both S_{i,a(j)} and S_{j,a(i)}.  Arguments as
+ * kkm_iterate without ldk; k <= 128 (else KKM_ERR_UNSUPPORTED); workspace of
+ * at least kkm_iterate_packed_workspace_bytes(n, k, k_store) (about
+ * k n^2 / (2 W) floats of per-row bins besides the step's partial sums).
+ * Asynchronous; deterministic.
+ *
+ * kkm_fit_packed — kkm_fit_ex with K strip-packed: K_ws (nullable) holds
+ * kkm_packed_elements(n, k_store) entries of k_store, else the library
+ * allocates them.  Synchronous; results and traces as kkm_fit_ex.
+ */
+size_t kkm_packed_elements(int64_t n, int32_t k_store);
+kkm_status kkm_gram_packed(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t kernel_type,
+                           double gamma, double coef0, int32_t degree, int32_t gram_prec,
+                           int32_t k_store, void *K, float *diagK, void *ws, size_t ws_bytes,
+                           void *stream);
+kkm_status kkm_iterate_packed(const void *K, int32_t k_store, const float *diagK, int64_t n,
+                              int32_t k, const int32_t *labels_in, int32_t empty_policy,
+                              int32_t *labels_out, int32_t *counts_out, int64_t *n_changed,
+                              double *J_in, float *D_out, float *ctilde_out, void *ws,
+                              size_t ws_bytes, void *stream);
+size_t kkm_iterate_packed_workspace_bytes(int64_t n, int32_t k, int32_t k_store);
+kkm_status kkm_fit_packed(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t k,
+                          int32_t kernel_type, double gamma, double coef0, int32_t degree,
+                          int32_t gram_prec, int32_t k_store, int32_t empty_policy,
+                          const int32_t *labels0, int32_t max_iter, int32_t check_convergence,
+                          int32_t *labels_out, double *objective, int32_t *iters, void *K_ws,
+                          double *J_trace, int64_t *changed_trace, double *times_ms, void *stream);
+
+/*
  * Launch timing for benchmarks (process-wide).  kkm_timing_enable(1) clears
  * the records and starts bracketing every Gram launch, every SpMM sweep launch
  * and every whole kkm_iterate step with HIP events on the caller's stream;

@@ -9,7 +9,9 @@ from ._binding import (BF16, EMPTY_INF, EMPTY_ZERO_CENTROID, EXPORTS, F32, FP8_R
                        LINEAR, MAX_K, POLY, KKMError, alloc_kernel_matrix, gram_workspace_bytes,
                        iterate_workspace_bytes, kkm_fit, kkm_fit_ex, kkm_gram, kkm_iterate,
                        kkm_iterate_noalloc, iterate_noalloc_max_bytes, kkm_iterate_matfree,
-                       kkm_fit_matfree, matfree_workspace_bytes,
+                       kkm_fit_matfree, matfree_workspace_bytes, kkm_gram_packed,
+                       kkm_iterate_packed, kkm_fit_packed, packed_elements, alloc_packed_kernel_matrix,
+                       packed_workspace_bytes,
                        kkm_timing_enable, kkm_timing_read, kkm_timing_spans, lib, mlp_param_count, kkm_mlp_forward,
                        kkm_mlp_loss_grad, kkm_mlp_adam, kkm_mlp_train, kkm_feature_lloyd,
                        kkm_feature_kmeanspp, kkm_mlp_train_fresh, kkm_fit_batched,
@@ -17,7 +19,9 @@ from ._binding import (BF16, EMPTY_INF, EMPTY_ZERO_CENTROID, EXPORTS, F32, FP8_R
                        GRAM_TRIANGLE, GRAM_FULL, GRAM_TRIANGLE_128, GRAM_TRIANGLE_256)
 
 __all__ = ["kkm_gram", "kkm_iterate", "kkm_iterate_noalloc", "iterate_noalloc_max_bytes", "kkm_iterate_matfree",
-           "kkm_fit_matfree", "matfree_workspace_bytes", "kkm_fit", "kkm_fit_ex", "kkm_timing_enable",
+           "kkm_fit_matfree", "matfree_workspace_bytes", "kkm_gram_packed",
+           "kkm_iterate_packed", "kkm_fit_packed", "packed_elements", "alloc_packed_kernel_matrix",
+           "packed_workspace_bytes", "kkm_fit", "kkm_fit_ex", "kkm_timing_enable",
            "kkm_timing_read", "kkm_timing_spans", "mlp_param_count", "kkm_mlp_forward", "kkm_mlp_loss_grad",
            "kkm_mlp_adam", "kkm_mlp_train", "kkm_feature_lloyd", "alloc_kernel_matrix",
            "gram_workspace_bytes", "iterate_workspace_bytes", "KKMError", "lib", "EXPORTS",

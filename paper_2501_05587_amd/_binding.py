@@ -25,6 +25,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkkm.so")
 EXPORTS = ("kkm_gram", "kkm_gram_ex", "kkm_gram_workspace_bytes", "kkm_iterate", "kkm_iterate_workspace_bytes",
            "kkm_iterate_noalloc", "kkm_iterate_noalloc_max_bytes",
            "kkm_iterate_matfree", "kkm_iterate_matfree_workspace_bytes", "kkm_fit_matfree",
+           "kkm_packed_elements", "kkm_gram_packed", "kkm_iterate_packed",
+           "kkm_iterate_packed_workspace_bytes", "kkm_fit_packed",
            "kkm_fit", "kkm_fit_ex", "kkm_mlp_param_count", "kkm_mlp_forward",
            "kkm_mlp_forward_workspace_bytes", "kkm_mlp_loss_grad", "kkm_mlp_train_workspace_bytes",
            "kkm_mlp_adam", "kkm_mlp_train", "kkm_feature_lloyd", "kkm_feature_lloyd_workspace_bytes",
@@ -89,6 +91,20 @@ def lib():
         L.kkm_fit_matfree.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _d, _d, _i32, _i32, _i32,
                                       _vp, _i32, _i32, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i32),
                                       _vp, _vp, _vp, _vp]
+        L.kkm_packed_elements.restype = _sz
+        L.kkm_packed_elements.argtypes = [_i64, _i32]
+        L.kkm_iterate_packed_workspace_bytes.restype = _sz
+        L.kkm_iterate_packed_workspace_bytes.argtypes = [_i64, _i32, _i32]
+        L.kkm_gram_packed.restype = ctypes.c_int
+        L.kkm_gram_packed.argtypes = [_vp, _i64, _i64, _i64, _i32, _d, _d, _i32, _i32, _i32, _vp, _vp,
+                                      _vp, _sz, _vp]
+        L.kkm_iterate_packed.restype = ctypes.c_int
+        L.kkm_iterate_packed.argtypes = [_vp, _i32, _vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp,
+                                         _vp, _vp, _vp, _sz, _vp]
+        L.kkm_fit_packed.restype = ctypes.c_int
+        L.kkm_fit_packed.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _d, _d, _i32, _i32, _i32,
+                                     _i32, _vp, _i32, _i32, _vp, ctypes.POINTER(_d),
+                                     ctypes.POINTER(_i32), _vp, _vp, _vp, _vp, _vp]
         L.kkm_fit.restype = ctypes.c_int
         L.kkm_fit.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _d, _d, _i32, _vp, _i32, _i32,
                               _vp, ctypes.POINTER(_d), ctypes.POINTER(_i32), _vp, _i64, _vp]
@@ -424,6 +440,115 @@ def kkm_fit_matfree(X, k, labels0, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1,
                                  _ptr(labels_out), ctypes.byref(J), ctypes.byref(it),
                                  Jt.ctypes.data_as(_vp), Ct.ctypes.data_as(_vp),
                                  tm.ctypes.data_as(_vp), _stream()))
+    t = int(it.value)
+    return dict(labels=labels_out, objective=J.value, iters=t, J_trace=Jt[:t + 1],
+                changed_trace=Ct[:t], times_ms=tm)
+
+
+def packed_elements(n: int, k_store: int = F32) -> int:
+    return int(lib().kkm_packed_elements(n, k_store))
+
+
+def alloc_packed_kernel_matrix(n: int, k_store=F32, device="cuda"):
+    """A 1-d device buffer for the strip-packed upper triangle of K."""
+    return torch.empty(packed_elements(n, k_store), dtype=_kstore_dtype(k_store), device=device)
+
+
+def packed_workspace_bytes(n: int, k: int, k_store: int = F32) -> int:
+    return int(lib().kkm_iterate_packed_workspace_bytes(n, k, k_store))
+
+
+def kkm_gram_packed(X, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram_prec=F32, k_store=F32,
+                    K=None, diagK=None, ws=None):
+    """K = kappa(X X^T) in the strip-packed upper layout, and diag(K).  Returns (K, diagK)."""
+    _dev(X, torch.float32, "X", 2)
+    n, d, ldx = _rows(X, "X")
+    if K is None:
+        K = alloc_packed_kernel_matrix(n, k_store, X.device)
+    _dev(K, _kstore_dtype(k_store), "K", 1)
+    if K.numel() < packed_elements(n, k_store):
+        raise ValueError("K holds fewer than packed_elements(n) entries")
+    if diagK is None:
+        diagK = torch.empty(n, dtype=torch.float32, device=X.device)
+    _dev(diagK, torch.float32, "diagK", 1)
+    need = gram_workspace_bytes(n, d, gram_prec)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    _check(lib().kkm_gram_packed(_ptr(X), n, d, ldx, kernel, gamma, coef0, degree, gram_prec,
+                                 k_store, _ptr(K), _ptr(diagK), _ptr(ws), ws.numel(), _stream()))
+    return K, diagK
+
+
+def kkm_iterate_packed(K, diagK, labels_in, k, empty_policy=EMPTY_INF, labels_out=None,
+                       counts_out=None, n_changed=None, J_in=None, D_out=None, ctilde_out=None,
+                       ws=None):
+    """One reassignment step on a strip-packed K (1-d, float32 or bfloat16)."""
+    k_store = BF16 if K.dtype == torch.bfloat16 else F32
+    _dev(K, _kstore_dtype(k_store), "K", 1)
+    _dev(diagK, torch.float32, "diagK", 1)
+    n = diagK.shape[0]
+    if K.numel() < packed_elements(n, k_store):
+        raise ValueError("K holds fewer than packed_elements(n) entries")
+    _dev(labels_in, torch.int32, "labels_in", 1)
+    dev = K.device
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=dev)
+    if counts_out is None:
+        counts_out = torch.empty(k, dtype=torch.int32, device=dev)
+    if n_changed is None:
+        n_changed = torch.empty(1, dtype=torch.int64, device=dev)
+    if J_in is None:
+        J_in = torch.empty(1, dtype=torch.float64, device=dev)
+    if D_out is True:
+        D_out = torch.empty((n, k), dtype=torch.float32, device=dev)
+    if ctilde_out is True:
+        ctilde_out = torch.empty(k, dtype=torch.float32, device=dev)
+    for t, dt, nm in ((labels_out, torch.int32, "labels_out"), (counts_out, torch.int32, "counts_out"),
+                      (n_changed, torch.int64, "n_changed"), (J_in, torch.float64, "J_in")):
+        _dev(t, dt, nm)
+    if D_out is not None:
+        _dev(D_out, torch.float32, "D_out", 2)
+        if not D_out.is_contiguous() or tuple(D_out.shape) != (n, k):
+            raise ValueError("D_out must be contiguous [n, k]")
+    if ctilde_out is not None:
+        _dev(ctilde_out, torch.float32, "ctilde_out", 1)
+    need = packed_workspace_bytes(n, k, k_store)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib().kkm_iterate_packed(_ptr(K), k_store, _ptr(diagK), n, k, _ptr(labels_in),
+                                    empty_policy, _ptr(labels_out), _ptr(counts_out),
+                                    _ptr(n_changed), _ptr(J_in), _ptr(D_out), _ptr(ctilde_out),
+                                    _ptr(ws), ws.numel(), _stream()))
+    return labels_out, counts_out, n_changed, J_in, D_out, ctilde_out
+
+
+def kkm_fit_packed(X, k, labels0, kernel=GAUSS, gamma=1.0, coef0=0.0, degree=1, gram_prec=F32,
+                   k_store=F32, empty_policy=EMPTY_INF, max_iter=30, check_convergence=True,
+                   K_ws=None, labels_out=None):
+    """kkm_fit_ex with K stored strip-packed (half the entries).  Returns a dict
+    with labels, objective, iters, J_trace, changed_trace and times_ms (Gram,
+    steps, final J)."""
+    import numpy as np
+
+    _dev(X, torch.float32, "X", 2)
+    n, d, ldx = _rows(X, "X")
+    _dev(labels0, torch.int32, "labels0", 1)
+    if labels_out is None:
+        labels_out = torch.empty(n, dtype=torch.int32, device=X.device)
+    if K_ws is not None:
+        _dev(K_ws, _kstore_dtype(k_store), "K_ws", 1)
+        if K_ws.numel() < packed_elements(n, k_store):
+            raise ValueError("K_ws holds fewer than packed_elements(n) entries")
+    J = _d()
+    it = _i32()
+    Jt = np.zeros(max_iter + 1, dtype=np.float64)
+    Ct = np.zeros(max(max_iter, 1), dtype=np.int64)
+    tm = np.zeros(3, dtype=np.float64)
+    _check(lib().kkm_fit_packed(_ptr(X), n, d, ldx, k, kernel, gamma, coef0, degree, gram_prec,
+                                k_store, empty_policy, _ptr(labels0), max_iter,
+                                int(bool(check_convergence)), _ptr(labels_out), ctypes.byref(J),
+                                ctypes.byref(it), _ptr(K_ws), Jt.ctypes.data_as(_vp),
+                                Ct.ctypes.data_as(_vp), tm.ctypes.data_as(_vp), _stream()))
     t = int(it.value)
     return dict(labels=labels_out, objective=J.value, iters=t, J_trace=Jt[:t + 1],
                 changed_trace=Ct[:t], times_ms=tm)

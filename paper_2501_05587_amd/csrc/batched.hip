@@ -425,6 +425,8 @@ void make_plan(const kkm_instance *inst, int32_t count, int32_t gram_prec, int32
         e.K = K[b];
         e.diag = p.diag + row_off[b];
         e.vec_k = 1;  // ldk is a multiple of 64 and each K starts 256-byte aligned
+        e.plgw = 0;
+        e.pns = 0;
         GramSrc &g = p.h_gtab[rnk];
         g.f.X = q.X;
         g.f.d = q.d;

@@ -78,7 +78,7 @@ size_t gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec) {
 kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t kernel,
                        double gamma, double coef0, int32_t degree, int32_t gram_prec,
                        int32_t k_store, void *K, int64_t ldk, float *diagK, void *ws,
-                       size_t ws_bytes, hipStream_t stream, int32_t shape) {
+                       size_t ws_bytes, hipStream_t stream, int32_t shape, bool packed) {
     const size_t need = gram_workspace_bytes(n, d, gram_prec);
     if (ws == nullptr || ws_bytes < need) {
         set_error("kkm_gram: workspace of %zu bytes is smaller than %zu", ws_bytes, need);
@@ -100,6 +100,18 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
     const uintptr_t kaddr = reinterpret_cast<uintptr_t>(K);
     e.vec_k = (k_store == KKM_F32) ? (((ldk % 4) == 0) && ((kaddr & 15) == 0))
                                    : (((ldk % 4) == 0) && ((kaddr & 7) == 0));
+    e.plgw = 0;
+    e.pns = 0;
+    if (packed) {
+        // strip-packed rows start at multiples of the strip width
+        e.plgw = packed_lgw(k_store);
+        e.pns = packed_strips(n, e.plgw);
+        e.vec_k = (k_store == KKM_F32) ? ((kaddr & 15) == 0) : ((kaddr & 7) == 0);
+        if (shape != KKM_GRAM_TRIANGLE && shape != KKM_GRAM_TRIANGLE_128) {
+            set_error("kkm_gram: a packed K is written by the 128 x 128 triangle only");
+            return KKM_ERR_UNSUPPORTED;
+        }
+    }
     const bool full = (shape == KKM_GRAM_FULL);
     // 256 x 256 tiles only on request: measured slower on MI355X at every n and
     // d tried (one workgroup per CU leaves the epilogue and the operand-load

@@ -39,7 +39,21 @@ struct Epi {
     void *K;
     float *diag;
     int vec_k;           // K rows aligned for 4-element stores
+    int plgw;            // strip-packed layout: log2 of the strip width (0: rows of stride ldk)
+    int64_t pns;         // strip-packed layout: strips
 };
+
+// Offset of K[i][j] (j at or right of the start of i's strip when packed).
+__device__ __forceinline__ int64_t k_index(const Epi &e, int64_t i, int64_t j) {
+    if (e.plgw == 0) return i * e.ldk + j;
+    return packed_row_offset(i, e.plgw, e.pns) + (j - ((i >> e.plgw) << e.plgw));
+}
+
+// Whether the mirrored block K[j][i] of tile (rows m0.., columns n0..) is
+// stored: always for rows of stride ldk, only inside a strip when packed.
+__device__ __forceinline__ bool mirror_stored(const Epi &e, int64_t m0, int64_t n0) {
+    return e.plgw == 0 || (m0 >> e.plgw) == (n0 >> e.plgw);
+}
 
 // The kernel's gamma as the epilogue takes it: for the Gaussian, gamma log2(e)
 // (rounded once, from double), so that exp(-gamma s) = 2^(-gamma log2(e) s) is
@@ -114,7 +128,7 @@ __device__ __forceinline__ void store_rows(const Epi &e, const float *T, int64_t
             const int64_t gi = row0 + (tid >> 5) + 8 * (8 * h + it);
             if (gi >= e.n) continue;
             const float v[4] = {w[it][0], w[it][1], w[it][2], w[it][3]};
-            const int64_t idx = gi * e.ldk + gj0;
+            const int64_t idx = k_index(e, gi, gj0);
             if (vec) {
                 Store<OUT>::four(e.K, idx, v);
             } else {
@@ -219,7 +233,8 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
                     }
                 }
             __syncthreads();
-            store_rows<OUT>(e, T, n0, m0);  // K[n0 + jj][m0 ..]; off the diagonal m0 + 127 < n0
+            // K[n0 + jj][m0 ..]; off the diagonal m0 + 127 < n0
+            if (mirror_stored(e, m0, n0)) store_rows<OUT>(e, T, n0, m0);
             __syncthreads();
             // as is: T[ii][jj]
 #pragma unroll
@@ -302,6 +317,7 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
             // diagonal m0 + 127 < n0
 #pragma unroll
             for (int h = 0; h < HALVES; ++h) {
+                if (!mirror_stored(e, m0, n0)) break;  // uniform: a packed K outside a strip
                 if (HALVES == 1 || wc == h) {
 #pragma unroll
                     for (int mi = 0; mi < 2; ++mi)
@@ -370,11 +386,11 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
                         const float dv = (e.kernel == KKM_GAUSS)
                                              ? (isfinite(b) ? 1.0f : __builtin_nanf(""))
                                              : Store<OUT>::round(v);
-                        Store<OUT>::one(e.K, gi * e.ldk + gi, dv);
+                        Store<OUT>::one(e.K, k_index(e, gi, gi), dv);
                         e.diag[gi] = dv;
                     } else {
-                        Store<OUT>::one(e.K, gi * e.ldk + gj, v);
-                        Store<OUT>::one(e.K, gj * e.ldk + gi, v);
+                        Store<OUT>::one(e.K, k_index(e, gi, gj), v);
+                        Store<OUT>::one(e.K, k_index(e, gj, gi), v);
                     }
                 }
             }
@@ -420,7 +436,8 @@ __device__ __forceinline__ void epilogue_keep(const Epi &e, f32x16 (&acc)[2][2],
             }
         }
     __syncthreads();
-    store_rows<OUT>(e, T, n0, m0);  // K[n0 + jj][m0 ..]; off the diagonal m0 + 127 < n0
+    // K[n0 + jj][m0 ..]; off the diagonal m0 + 127 < n0
+    if (mirror_stored(e, m0, n0)) store_rows<OUT>(e, T, n0, m0);
     __syncthreads();
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)

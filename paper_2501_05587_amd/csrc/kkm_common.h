@@ -61,11 +61,13 @@ void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream);
 
 size_t gram_workspace_bytes(int64_t n, int64_t d, int32_t gram_prec);
 // shape: KKM_GRAM_TRIANGLE (upper-triangle tiles, mirrored stores) or
-// KKM_GRAM_FULL (every tile, each storing its own block).
+// KKM_GRAM_FULL (every tile, each storing its own block).  packed: K in the
+// strip-packed upper layout (packed_row_offset; ldk unused), triangle only.
 kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_t kernel,
                        double gamma, double coef0, int32_t degree, int32_t gram_prec,
                        int32_t k_store, void *K, int64_t ldk, float *diagK, void *ws,
-                       size_t ws_bytes, hipStream_t stream, int32_t shape = KKM_GRAM_TRIANGLE);
+                       size_t ws_bytes, hipStream_t stream, int32_t shape = KKM_GRAM_TRIANGLE,
+                       bool packed = false);
 
 // The loop of Algorithm 2 around a step function: steps from labels0 until
 // no label changes (check_convergence != 0) or max_iter steps, then the
@@ -81,6 +83,26 @@ kkm_status run_steps(const StepFn &step, size_t step_ws, int64_t n, int32_t k,
                      const int32_t *labels0, int32_t max_iter, int32_t check_convergence,
                      int32_t *labels_out, double *objective, int32_t *iters, double *J_trace,
                      int64_t *changed_trace, double *times_ms, const char *who, hipStream_t s);
+
+// ---------------------------------------------------------------- strip-packed symmetric K
+// The upper triangle of K in strips of W columns (W a power of two): row i,
+// in strip s_i = i / W, stores the columns [s_i W, ns W) of its row, so the
+// diagonal W x W block of every strip is stored whole (both triangles) and
+// every block above it once.  Rows follow each other; element (i, j) with
+// j >= s_i W sits at packed_row_offset(i) + (j - s_i W).  ns W elements per
+// row of strip 0, (ns - s) W per row of strip s: W^2 ns (ns + 1) / 2 in all.
+__host__ __device__ inline int64_t packed_row_offset(int64_t i, int lgw, int64_t ns) {
+    const int64_t W = int64_t(1) << lgw;
+    const int64_t s = i >> lgw;
+    return W * W * (s * ns - s * (s - 1) / 2) + (i - s * W) * (ns - s) * W;
+}
+inline int64_t packed_strips(int64_t n, int lgw) { return (n + (int64_t(1) << lgw) - 1) >> lgw; }
+inline int64_t packed_elements(int64_t n, int lgw) {
+    const int64_t W = int64_t(1) << lgw, ns = packed_strips(n, lgw);
+    return W * W * ns * (ns + 1) / 2;
+}
+// Strip width of the packed layout for K stored as FP32 (1024) or bfloat16 (2048).
+inline int packed_lgw(int32_t k_store) { return k_store == KKM_BF16 ? 11 : 10; }
 
 // ---------------------------------------------------------------- workspace carving
 
