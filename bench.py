@@ -61,12 +61,12 @@ BF16_MFMA_PEAK_TFS = 2500.0
 # recorded value; otherwise the traffic is reported as null.
 TRAFFIC = {
     "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
-                       "sha256": "5dfa764ff32bcad8404bb7b0d925b865fc7dfd0af7fedd260eee0ae69eda4208",
-                       "n": 200000, "fetch_kib": 78169660.7, "write_kib": 85552.3,
+                       "sha256": "e41ef9ea21834fec006f837abf498909ed9c90ff1eadf490973f6ce25bd01c1f",
+                       "n": 200000, "fetch_kib": 78170000.0, "write_kib": 89550.0,
                        "fetch_scale": 1.9999, "write_scale": 1.0},
     "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_f32.hip", "csrc/gram_tile.h", "csrc/kkm_common.h"],
-                      "sha256": "50f85bd9f32aa068be140202f556027e826462f5f6b4933083f3e8d392393e86",
-                      "n": 200000, "fetch_kib": 160830564.2, "write_kib": 156250900.2,
+                      "sha256": "7e989430ed7304f47b79b1469f4612f63795ab2f06251711c884852291d5bee2",
+                      "n": 200000, "fetch_kib": 152000000.0, "write_kib": 156300000.0,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }
 

@@ -28,13 +28,13 @@ namespace kkm {
 namespace {
 
 constexpr int PK_THREADS = 256;       // 4 waves, each walking its own rows over the whole strip
-constexpr int PK_ROWS = 2;            // rows per wave pass
 constexpr int PK_MAXK = 128;          // bins per row
 
 
 template <typename T> struct PkRow;
 template <> struct PkRow<float> {
-    static constexpr int E = 4;  // elements per 16-byte load
+    static constexpr int E = 4;     // elements per 16-byte load
+    static constexpr int ROWS = 2;  // rows per wave pass (4: two waves per SIMD instead of three, slower)
     static __device__ __forceinline__ void unpack(const uint4 &w, float (&v)[E]) {
         v[0] = __uint_as_float(w.x);
         v[1] = __uint_as_float(w.y);
@@ -44,6 +44,7 @@ template <> struct PkRow<float> {
 };
 template <> struct PkRow<uint16_t> {
     static constexpr int E = 8;
+    static constexpr int ROWS = 2;
     static __device__ __forceinline__ void unpack(const uint4 &w, float (&v)[E]) {
         const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -83,6 +84,7 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
     constexpr int C = 4 * E;        // columns per lane
     constexpr int W = kWave * C;    // strip width (1024 FP32, 2048 bfloat16)
     constexpr int G = W / 256;      // 256-column groups of the own-cluster sums
+    constexpr int PK_ROWS = PkRow<T>::ROWS;  // rows per wave pass
     // per wave: the staged row in sorted order, then the run sums; the flush
     // reuses the same memory for the other waves' column sums
     __shared__ __attribute__((aligned(16))) float stage[4][2][W];
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
                     for (int u = 0; u < 4; ++u) raw[r][u] = make_uint4(0, 0, 0, 0);
                 }
             }
-            // column part: the pass's two rows added, then compensated
+            // column part: the pass's rows added pairwise, then compensated
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 float f[PK_ROWS][E];
@@ -213,7 +215,8 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
                 for (int r = 0; r < PK_ROWS; ++r) PkRow<T>::unpack(raw[r][u], f[r]);
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    const float b = f[0][e] + f[1][e];
+                    float b = f[0][e] + f[1][e];
+                    if constexpr (PK_ROWS == 4) b += f[2][e] + f[3][e];
                     float t, er;
                     two_sum(sum[u * E + e], b, t, er);
                     sum[u * E + e] = t;
@@ -234,24 +237,22 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // this lane's sorted chunk, summed run by run
+                // this lane's sorted chunk: running sums that restart where a run
+                // starts, so the value at a run's last position in the lane is
+                // that run's piece (branch-free; every position is written)
                 float acc = 0.f;
-                int rs = 0;
 #pragma unroll
                 for (int e4 = 0; e4 < C / 4; ++e4) {
                     const f32x4 w = *reinterpret_cast<const f32x4 *>(stg + lane * C + 4 * e4);
+                    f32x4 o;
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
                         const int e = 4 * e4 + b;
-                        if (e > 0 && ((runbits >> e) & 1u)) {
-                            part[lane * C + rs] = acc;
-                            acc = 0.f;
-                            rs = e;
-                        }
-                        acc += w[b];
+                        acc = ((runbits >> e) & 1u) ? w[b] : acc + w[b];
+                        o[b] = acc;
                     }
+                    *reinterpret_cast<f32x4 *>(part + lane * C + 4 * e4) = o;
                 }
-                part[lane * C + rs] = acc;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -261,10 +262,9 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
                 for (int t = lane; t < k; t += kWave) {
                     const int32_t a0 = cstart[t], a1 = cstart[t + 1];
                     float v = 0.f;
-                    if (a1 > a0) {
-                        v = part[a0];
-                        for (int32_t pos = (a0 / C + 1) * C; pos < a1; pos += C) v += part[pos];
-                    }
+                    if (a1 > a0)
+                        for (int32_t L0 = a0 - a0 % C; L0 < a1; L0 += C)
+                            v += part[min(a1, L0 + C) - 1];  // the run's piece in the lane at L0
                     dst[t] = v;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
