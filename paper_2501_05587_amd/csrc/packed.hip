@@ -105,7 +105,7 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t col0 = s * W;
 
     // ---- the strip's columns sorted by label (stable): rank[] and cstart[]
@@ -185,17 +185,32 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
     while (p < p_end) {
         while (offsets[c + 1] <= p) ++c;  // skip empty clusters
         const int64_t seg_end = min(p_end, (int64_t)offsets[c + 1]);
-        for (int64_t pp = p + wave; pp < seg_end; pp += 4 * PK_ROWS) {
+        // wave w takes positions pp .. pp + PK_ROWS - 1 of every 4 PK_ROWS; a
+        // segment lists its points in increasing order (the CSR build is a
+        // stable sort), so once a row lies right of strip s, so do the rest
+        // of the segment and the wave is done with it
+        int64_t jn[PK_ROWS];
+#pragma unroll
+        for (int r = 0; r < PK_ROWS; ++r) {
+            const int64_t pr = p + wave * PK_ROWS + r;
+            jn[r] = (pr < seg_end) ? (int64_t)perm[pr] : -1;
+        }
+        for (int64_t pp = p + wave * PK_ROWS; pp < seg_end; pp += 4 * PK_ROWS) {
+            if ((jn[0] >> a.lgw) > s) break;
             uint4 raw[PK_ROWS][4];
             int64_t jr[PK_ROWS];
             bool up[PK_ROWS];
 #pragma unroll
+            for (int r = 0; r < PK_ROWS; ++r) jr[r] = jn[r];
+#pragma unroll
+            for (int r = 0; r < PK_ROWS; ++r) {  // the next pass's rows, ahead of use
+                const int64_t pr = pp + 4 * PK_ROWS + r;
+                jn[r] = (pr < seg_end) ? (int64_t)perm[pr] : -1;
+            }
+#pragma unroll
             for (int r = 0; r < PK_ROWS; ++r) {
-                const int64_t pr = pp + 4 * r;
-                int64_t j = -1;
-                if (pr < seg_end) j = __builtin_amdgcn_readfirstlane(perm[pr]);
+                const int64_t j = jr[r];
                 const int64_t sj = (j >= 0) ? (j >> a.lgw) : ns;
-                jr[r] = j;
                 up[r] = sj < s;
                 if (sj <= s) {
                     const T *row = K + packed_row_offset(j, a.lgw, ns) + (s - sj) * W + lane * E;
