@@ -35,6 +35,7 @@ template <typename T> struct PkRow;
 template <> struct PkRow<float> {
     static constexpr int E = 4;     // elements per 16-byte load
     static constexpr int ROWS = 2;  // rows per wave pass (4: two waves per SIMD instead of three, slower)
+    static constexpr bool PREFETCH = true;  // next pass's rows loaded before this pass's row part
     static __device__ __forceinline__ void unpack(const uint4 &w, float (&v)[E]) {
         v[0] = __uint_as_float(w.x);
         v[1] = __uint_as_float(w.y);
@@ -45,6 +46,7 @@ template <> struct PkRow<float> {
 template <> struct PkRow<uint16_t> {
     static constexpr int E = 8;
     static constexpr int ROWS = 2;
+    static constexpr bool PREFETCH = false;  // a second set of rows would spill
     static __device__ __forceinline__ void unpack(const uint4 &w, float (&v)[E]) {
         const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -85,6 +87,7 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
     constexpr int W = kWave * C;    // strip width (1024 FP32, 2048 bfloat16)
     constexpr int G = W / 256;      // 256-column groups of the own-cluster sums
     constexpr int PK_ROWS = PkRow<T>::ROWS;  // rows per wave pass
+    static_assert(PK_ROWS == 2, "the row part stages the pass's two rows as pairs");
     // per wave: the staged row in sorted order, then the run sums; the flush
     // reuses the same memory for the other waves' column sums
     __shared__ __attribute__((aligned(16))) float stage[4][2][W];
@@ -132,8 +135,17 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
     }
     __syncthreads();
 
+    // Staging slot (in pairs of floats) of sorted position P: the chunk of
+    // lane P / C, whose 16-byte slots (two positions each) are rotated by that
+    // lane so that eight neighbouring lanes reading their chunks in step touch
+    // different banks.
+    auto staged = [](int P) -> int {
+        const int L = P / C, o = P % C;
+        return L * C + ((((o >> 1) ^ (L & 7)) << 1) | (o & 1));
+    };
     // this lane's columns: col0 + u 64 E + lane E + e (u < 4, e < E); their
-    // labels (own-cluster sums) and sorted positions, packed
+    // labels (own-cluster sums) and staging slots of their sorted positions,
+    // packed
     uint32_t labp[C / 4];
     uint32_t rk[C / 2];
 #pragma unroll
@@ -149,8 +161,8 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
 #pragma unroll
     for (int t = 0; t < C / 2; ++t) {
         const int i0 = 2 * t, i1 = 2 * t + 1;
-        rk[t] = (uint32_t)rank[(i0 / E) * (kWave * E) + lane * E + (i0 % E)] |
-                ((uint32_t)rank[(i1 / E) * (kWave * E) + lane * E + (i1 % E)] << 16);
+        rk[t] = (uint32_t)staged(rank[(i0 / E) * (kWave * E) + lane * E + (i0 % E)]) |
+                ((uint32_t)staged(rank[(i1 / E) * (kWave * E) + lane * E + (i1 % E)]) << 16);
     }
     auto lab_of = [&](int idx) -> uint32_t { return (labp[idx >> 2] >> (8 * (idx & 3))) & 0xFFu; };
     auto rank_of = [&](int idx) -> uint32_t { return (rk[idx >> 1] >> (16 * (idx & 1))) & 0xFFFFu; };
@@ -166,8 +178,7 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
             if (e > 0 && cstart[t] == pos) runbits |= 1u << e;
         }
     }
-    float *const stg = &stage[wave][0][0];
-    float *const part = &stage[wave][1][0];
+    float *const stg = &stage[wave][0][0];  // 2 W floats: a pair per sorted position
 
     float sum[C], comp[C];
 #pragma unroll
@@ -189,31 +200,18 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
         // segment lists its points in increasing order (the CSR build is a
         // stable sort), so once a row lies right of strip s, so do the rest
         // of the segment and the wave is done with it
-        int64_t jn[PK_ROWS];
+        auto rows_at = [&](int64_t pr0, int64_t (&jj)[PK_ROWS]) {
 #pragma unroll
-        for (int r = 0; r < PK_ROWS; ++r) {
-            const int64_t pr = p + wave * PK_ROWS + r;
-            jn[r] = (pr < seg_end) ? (int64_t)perm[pr] : -1;
-        }
-        for (int64_t pp = p + wave * PK_ROWS; pp < seg_end; pp += 4 * PK_ROWS) {
-            if ((jn[0] >> a.lgw) > s) break;
-            uint4 raw[PK_ROWS][4];
-            int64_t jr[PK_ROWS];
-            bool up[PK_ROWS];
-#pragma unroll
-            for (int r = 0; r < PK_ROWS; ++r) jr[r] = jn[r];
-#pragma unroll
-            for (int r = 0; r < PK_ROWS; ++r) {  // the next pass's rows, ahead of use
-                const int64_t pr = pp + 4 * PK_ROWS + r;
-                jn[r] = (pr < seg_end) ? (int64_t)perm[pr] : -1;
-            }
+            for (int r = 0; r < PK_ROWS; ++r)
+                jj[r] = (pr0 + r < seg_end) ? (int64_t)perm[pr0 + r] : -1;
+        };
+        // the rows' segments in strip s (zeros for rows right of it or past the segment)
+        auto fetch = [&](const int64_t (&jj)[PK_ROWS], uint4 (&raw)[PK_ROWS][4]) {
 #pragma unroll
             for (int r = 0; r < PK_ROWS; ++r) {
-                const int64_t j = jr[r];
-                const int64_t sj = (j >= 0) ? (j >> a.lgw) : ns;
-                up[r] = sj < s;
+                const int64_t sj = (jj[r] >= 0) ? (jj[r] >> a.lgw) : ns;
                 if (sj <= s) {
-                    const T *row = K + packed_row_offset(j, a.lgw, ns) + (s - sj) * W + lane * E;
+                    const T *row = K + packed_row_offset(jj[r], a.lgw, ns) + (s - sj) * W + lane * E;
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
                         raw[r][u] = *reinterpret_cast<const uint4 *>(row + u * (kWave * E));
@@ -221,6 +219,27 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
 #pragma unroll
                     for (int u = 0; u < 4; ++u) raw[r][u] = make_uint4(0, 0, 0, 0);
                 }
+            }
+        };
+        // row indices two passes ahead, row segments one pass ahead (PREFETCH)
+        const int64_t pp0 = p + wave * PK_ROWS;
+        int64_t jc[PK_ROWS], jn[PK_ROWS];
+        rows_at(pp0, jc);
+        rows_at(pp0 + 4 * PK_ROWS, jn);
+        uint4 raw[PK_ROWS][4];
+        fetch(jc, raw);
+        for (int64_t pp = pp0; pp < seg_end; pp += 4 * PK_ROWS) {
+            if ((jc[0] >> a.lgw) > s) break;
+            uint4 nxt[PK_ROWS][4];
+            if constexpr (PkRow<T>::PREFETCH) fetch(jn, nxt);
+            int64_t jq[PK_ROWS];
+            rows_at(pp + 8 * PK_ROWS, jq);
+            int64_t jr[PK_ROWS];
+            bool up[PK_ROWS];
+#pragma unroll
+            for (int r = 0; r < PK_ROWS; ++r) {
+                jr[r] = jc[r];
+                up[r] = jc[r] >= 0 && (jc[r] >> a.lgw) < s;
             }
             // column part: the pass's rows added pairwise, then compensated
 #pragma unroll
@@ -231,60 +250,90 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     float b = f[0][e] + f[1][e];
-                    if constexpr (PK_ROWS == 4) b += f[2][e] + f[3][e];
                     float t, er;
                     two_sum(sum[u * E + e], b, t, er);
                     sum[u * E + e] = t;
                     comp[u * E + e] += er;
                 }
             }
-            // row part, one row at a time
-#pragma unroll
-            for (int r = 0; r < PK_ROWS; ++r) {
-                if (!up[r]) continue;  // wave-uniform
+            // row part, the pass's two rows together: each sorted position holds
+            // the pair (row 0, row 1) (rows not left of the strip carry values
+            // that are summed but not stored)
+            if (up[0] || up[1]) {  // wave-uniform
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    float f[E];
-                    PkRow<T>::unpack(raw[r][u], f);
+                    float f0[E], f1[E];
+                    PkRow<T>::unpack(raw[0][u], f0);
+                    PkRow<T>::unpack(raw[1][u], f1);
 #pragma unroll
-                    for (int e = 0; e < E; ++e) stg[rank_of(u * E + e)] = f[e];
+                    for (int e = 0; e < E; ++e)
+                        *reinterpret_cast<float2 *>(stg + 2 * rank_of(u * E + e)) =
+                            make_float2(f0[e], f1[e]);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // this lane's sorted chunk: running sums that restart where a run
-                // starts, so the value at a run's last position in the lane is
-                // that run's piece (branch-free; every position is written)
-                float acc = 0.f;
+                // this lane's sorted chunk, in place: running sums that restart
+                // where a run starts, so the value at a run's last position in
+                // the lane is that run's piece (branch-free; every position is
+                // written)
+                float acc0 = 0.f, acc1 = 0.f;
 #pragma unroll
-                for (int e4 = 0; e4 < C / 4; ++e4) {
-                    const f32x4 w = *reinterpret_cast<const f32x4 *>(stg + lane * C + 4 * e4);
+                for (int e2 = 0; e2 < C / 2; ++e2) {
+                    float *slot = stg + 2 * (lane * C) + 4 * (e2 ^ (lane & 7));
+                    const f32x4 w = *reinterpret_cast<const f32x4 *>(slot);
+                    const int ea = 2 * e2, eb = 2 * e2 + 1;
                     f32x4 o;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int e = 4 * e4 + b;
-                        acc = ((runbits >> e) & 1u) ? w[b] : acc + w[b];
-                        o[b] = acc;
-                    }
-                    *reinterpret_cast<f32x4 *>(part + lane * C + 4 * e4) = o;
+                    acc0 = ((runbits >> ea) & 1u) ? w[0] : acc0 + w[0];
+                    acc1 = ((runbits >> ea) & 1u) ? w[1] : acc1 + w[1];
+                    o[0] = acc0;
+                    o[1] = acc1;
+                    acc0 = ((runbits >> eb) & 1u) ? w[2] : acc0 + w[2];
+                    acc1 = ((runbits >> eb) & 1u) ? w[3] : acc1 + w[3];
+                    o[2] = acc0;
+                    o[3] = acc1;
+                    *reinterpret_cast<f32x4 *>(slot) = o;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 // cluster t: its run's pieces, lane by lane
-                float *dst = a.R + rowpart_offset(jr[r], a.lgw, ns, k) +
-                             (s - (jr[r] >> a.lgw) - 1) * (int64_t)k;
+                float *dst0 = up[0] ? a.R + rowpart_offset(jr[0], a.lgw, ns, k) +
+                                          (s - (jr[0] >> a.lgw) - 1) * (int64_t)k
+                                    : nullptr;
+                float *dst1 = up[1] ? a.R + rowpart_offset(jr[1], a.lgw, ns, k) +
+                                          (s - (jr[1] >> a.lgw) - 1) * (int64_t)k
+                                    : nullptr;
                 for (int t = lane; t < k; t += kWave) {
                     const int32_t a0 = cstart[t], a1 = cstart[t + 1];
-                    float v = 0.f;
+                    float v0 = 0.f, v1 = 0.f;
                     if (a1 > a0)
-                        for (int32_t L0 = a0 - a0 % C; L0 < a1; L0 += C)
-                            v += part[min(a1, L0 + C) - 1];  // the run's piece in the lane at L0
-                    dst[t] = v;
+                        for (int32_t L0 = a0 - a0 % C; L0 < a1; L0 += C) {
+                            // the run's piece in the lane at L0
+                            const float2 pc =
+                                *reinterpret_cast<const float2 *>(stg + 2 * staged(min(a1, L0 + C) - 1));
+                            v0 += pc.x;
+                            v1 += pc.y;
+                        }
+                    if (up[0]) dst0[t] = v0;
+                    if (up[1]) dst1[t] = v1;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            if constexpr (PkRow<T>::PREFETCH) {
+#pragma unroll
+                for (int r = 0; r < PK_ROWS; ++r)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) raw[r][u] = nxt[r][u];
+            } else {
+                fetch(jn, raw);
+            }
+#pragma unroll
+            for (int r = 0; r < PK_ROWS; ++r) {
+                jc[r] = jn[r];
+                jn[r] = jq[r];
             }
         }
         // flush segment (q, c): the four waves' column sums, added in wave order
