@@ -35,7 +35,7 @@ template <typename T> struct PkRow;
 template <> struct PkRow<float> {
     static constexpr int E = 4;     // elements per 16-byte load
     static constexpr int ROWS = 2;  // rows per wave pass (4: two waves per SIMD instead of three, slower)
-    static constexpr bool PREFETCH = true;  // next pass's rows loaded before this pass's row part
+    static constexpr int BLOCKS = 3;  // workgroups per CU (VGPR budget)
     static __device__ __forceinline__ void unpack(const uint4 &w, float (&v)[E]) {
         v[0] = __uint_as_float(w.x);
         v[1] = __uint_as_float(w.y);
@@ -46,7 +46,7 @@ template <> struct PkRow<float> {
 template <> struct PkRow<uint16_t> {
     static constexpr int E = 8;
     static constexpr int ROWS = 2;
-    static constexpr bool PREFETCH = false;  // a second set of rows would spill
+    static constexpr int BLOCKS = 2;
     static __device__ __forceinline__ void unpack(const uint4 &w, float (&v)[E]) {
         const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -71,6 +71,24 @@ __host__ __device__ inline int64_t rowpart_offset(int64_t j, int lgw, int64_t ns
     return (int64_t)k * (W * (s * (ns - 1) - s * (s - 1) / 2) + (j - s * W) * (ns - s - 1));
 }
 
+// Offset of row j's segment in strip s (s >= s_j) in the packed K, in
+// elements: packed_row_offset(j) + (s - s_j) W, taken with 32-bit partial
+// products (ns < 2^16 is checked on the host).
+__device__ __forceinline__ int64_t pk_segment(uint32_t j, int lgw, uint32_t ns, uint32_t s) {
+    const uint32_t sj = j >> lgw, u = j - (sj << lgw);
+    const uint32_t tri = sj * ns - ((sj * (sj - 1)) >> 1);
+    return ((int64_t)tri << (2 * lgw)) + ((int64_t)(u * (ns - sj) + (s - sj)) << lgw);
+}
+
+// Offset of row j's k row-part sums for strip s (s > s_j), in floats:
+// rowpart_offset(j) + (s - s_j - 1) k, as above.
+__device__ __forceinline__ int64_t pk_rowpart(uint32_t j, int lgw, uint32_t ns, uint32_t s,
+                                              int32_t k) {
+    const uint32_t sj = j >> lgw, u = j - (sj << lgw);
+    const uint32_t tri = sj * (ns - 1) - ((sj * (sj - 1)) >> 1);
+    return (int64_t)k * (((int64_t)tri << lgw) + (int64_t)(u * (ns - sj - 1) + (s - sj - 1)));
+}
+
 // One work item = (strip s, chunk q of L positions in V's CSR order).
 //
 // The row part of a row left of the strip: the row's W values are written to
@@ -80,7 +98,7 @@ __host__ __device__ inline int64_t rowpart_offset(int64_t j, int lgw, int64_t ns
 // and each cluster's run sums are added over the lanes its run spans, in lane
 // order: no atomics, and every sum is taken in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
+__global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkArgs a, Inst in,
                                                            const int32_t *labels) {
     constexpr int E = PkRow<T>::E;
     constexpr int C = 4 * E;        // columns per lane
@@ -98,8 +116,11 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
     const int64_t n = in.n;
     const int32_t k = in.k;
     const int64_t ns = a.ns;
-    const int64_t s = blockIdx.x % ns;
-    const int64_t q = blockIdx.x / ns;
+    // items by decreasing strip: an item of strip s reads the rows of strips
+    // 0 .. s, so the longest items start first and the short ones fill the end
+    const int64_t nq = (n + in.L - 1) / in.L;
+    const int64_t s = ns - 1 - (int64_t)blockIdx.x / nq;
+    const int64_t q = (int64_t)blockIdx.x % nq;
     const int64_t p_begin = q * in.L;
     const int64_t p_end = min(n, p_begin + in.L);
     const int32_t *__restrict__ perm = in.perm;
@@ -178,6 +199,24 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
             if (e > 0 && cstart[t] == pos) runbits |= 1u << e;
         }
     }
+    // Cluster t = lane + 64 h (h < 2: k <= 128) has its run in the chunks of
+    // lanes a0 / C .. (a1 - 1) / C; its piece in each is the running sum at the
+    // chunk's last position, or at a1 - 1 in the run's last chunk.  The staging
+    // slots of the first three pieces and their count, packed by 16 bits.
+    uint32_t pc01[2], pc2n[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int t = lane + kWave * h;
+        const int32_t a0 = (t < k) ? cstart[t] : 0, a1 = (t < k) ? cstart[t + 1] : 0;
+        const int32_t np = (a1 > a0) ? (a1 - 1) / C - a0 / C + 1 : 0;
+        auto piece = [&](int32_t m) -> uint32_t {
+            return (uint32_t)staged(m == np - 1 ? a1 - 1 : (a0 / C + m + 1) * C - 1);
+        };
+        const uint32_t p0 = np > 0 ? piece(0) : 0u;
+        const uint32_t p1 = np > 1 ? piece(1) : p0, p2 = np > 2 ? piece(2) : p0;
+        pc01[h] = p0 | (p1 << 16);
+        pc2n[h] = p2 | ((uint32_t)np << 16);
+    }
     float *const stg = &stage[wave][0][0];  // 2 W floats: a pair per sorted position
 
     float sum[C], comp[C];
@@ -192,55 +231,42 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
     }
     int32_t c = lo;
 
-    int64_t p = p_begin;
+    const uint32_t s32 = (uint32_t)s, ns32 = (uint32_t)ns;
+    const int lgw = a.lgw;
+    int32_t p = (int32_t)p_begin;
     while (p < p_end) {
         while (offsets[c + 1] <= p) ++c;  // skip empty clusters
-        const int64_t seg_end = min(p_end, (int64_t)offsets[c + 1]);
+        const int32_t seg_end = min((int32_t)p_end, offsets[c + 1]);
         // wave w takes positions pp .. pp + PK_ROWS - 1 of every 4 PK_ROWS; a
         // segment lists its points in increasing order (the CSR build is a
         // stable sort), so once a row lies right of strip s, so do the rest
         // of the segment and the wave is done with it
-        auto rows_at = [&](int64_t pr0, int64_t (&jj)[PK_ROWS]) {
+        auto rows_at = [&](int32_t pr0, int32_t (&jj)[PK_ROWS]) {
 #pragma unroll
-            for (int r = 0; r < PK_ROWS; ++r)
-                jj[r] = (pr0 + r < seg_end) ? (int64_t)perm[pr0 + r] : -1;
+            for (int r = 0; r < PK_ROWS; ++r) jj[r] = (pr0 + r < seg_end) ? perm[pr0 + r] : -1;
         };
-        // the rows' segments in strip s (zeros for rows right of it or past the segment)
-        auto fetch = [&](const int64_t (&jj)[PK_ROWS], uint4 (&raw)[PK_ROWS][4]) {
+        // the rows' segments in strip s: buffer loads whose range is empty
+        // (so they read zeros) for a row right of the strip or past the segment
+        auto fetch = [&](const int32_t (&jj)[PK_ROWS], uint4 (&raw)[PK_ROWS][4]) {
 #pragma unroll
             for (int r = 0; r < PK_ROWS; ++r) {
-                const int64_t sj = (jj[r] >= 0) ? (jj[r] >> a.lgw) : ns;
-                if (sj <= s) {
-                    const T *row = K + packed_row_offset(jj[r], a.lgw, ns) + (s - sj) * W + lane * E;
+                const bool here = jj[r] >= 0 && ((uint32_t)jj[r] >> lgw) <= s32;
+                const T *row = here ? K + pk_segment((uint32_t)jj[r], lgw, ns32, s32) : K;
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<T *>(row), (short)0, here ? (int)(W * sizeof(T)) : 0, 0x00020000);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        raw[r][u] = *reinterpret_cast<const uint4 *>(row + u * (kWave * E));
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) raw[r][u] = make_uint4(0, 0, 0, 0);
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t off = (uint32_t)((u * kWave + lane) * E * sizeof(T));
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+                    raw[r][u] = make_uint4(w[0], w[1], w[2], w[3]);
                 }
             }
         };
-        // row indices two passes ahead, row segments one pass ahead (PREFETCH)
-        const int64_t pp0 = p + wave * PK_ROWS;
-        int64_t jc[PK_ROWS], jn[PK_ROWS];
-        rows_at(pp0, jc);
-        rows_at(pp0 + 4 * PK_ROWS, jn);
-        uint4 raw[PK_ROWS][4];
-        fetch(jc, raw);
-        for (int64_t pp = pp0; pp < seg_end; pp += 4 * PK_ROWS) {
-            if ((jc[0] >> a.lgw) > s) break;
-            uint4 nxt[PK_ROWS][4];
-            if constexpr (PkRow<T>::PREFETCH) fetch(jn, nxt);
-            int64_t jq[PK_ROWS];
-            rows_at(pp + 8 * PK_ROWS, jq);
-            int64_t jr[PK_ROWS];
+        // one pass: the column part of the pass's rows, then their row part
+        auto process = [&](const uint4 (&raw)[PK_ROWS][4], const int32_t (&jr)[PK_ROWS]) {
             bool up[PK_ROWS];
 #pragma unroll
-            for (int r = 0; r < PK_ROWS; ++r) {
-                jr[r] = jc[r];
-                up[r] = jc[r] >= 0 && (jc[r] >> a.lgw) < s;
-            }
+            for (int r = 0; r < PK_ROWS; ++r) up[r] = jr[r] >= 0 && ((uint32_t)jr[r] >> lgw) < s32;
             // column part: the pass's rows added pairwise, then compensated
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -259,82 +285,99 @@ __global__ __launch_bounds__(PK_THREADS, 2) void packed_sweep(PkArgs a, Inst in,
             // row part, the pass's two rows together: each sorted position holds
             // the pair (row 0, row 1) (rows not left of the strip carry values
             // that are summed but not stored)
-            if (up[0] || up[1]) {  // wave-uniform
+            if (!(up[0] || up[1])) return;  // wave-uniform
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    float f0[E], f1[E];
-                    PkRow<T>::unpack(raw[0][u], f0);
-                    PkRow<T>::unpack(raw[1][u], f1);
+            for (int u = 0; u < 4; ++u) {
+                float f0[E], f1[E];
+                PkRow<T>::unpack(raw[0][u], f0);
+                PkRow<T>::unpack(raw[1][u], f1);
 #pragma unroll
-                    for (int e = 0; e < E; ++e)
-                        *reinterpret_cast<float2 *>(stg + 2 * rank_of(u * E + e)) =
-                            make_float2(f0[e], f1[e]);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // this lane's sorted chunk, in place: running sums that restart
-                // where a run starts, so the value at a run's last position in
-                // the lane is that run's piece (branch-free; every position is
-                // written)
-                float acc0 = 0.f, acc1 = 0.f;
+                for (int e = 0; e < E; ++e)
+                    *reinterpret_cast<float2 *>(stg + 2 * rank_of(u * E + e)) = make_float2(f0[e], f1[e]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // this lane's sorted chunk, in place: running sums that restart
+            // where a run starts, so the value at a run's last position in
+            // the lane is that run's piece (branch-free; every position is
+            // written)
+            float acc0 = 0.f, acc1 = 0.f;
 #pragma unroll
-                for (int e2 = 0; e2 < C / 2; ++e2) {
-                    float *slot = stg + 2 * (lane * C) + 4 * (e2 ^ (lane & 7));
-                    const f32x4 w = *reinterpret_cast<const f32x4 *>(slot);
-                    const int ea = 2 * e2, eb = 2 * e2 + 1;
-                    f32x4 o;
-                    acc0 = ((runbits >> ea) & 1u) ? w[0] : acc0 + w[0];
-                    acc1 = ((runbits >> ea) & 1u) ? w[1] : acc1 + w[1];
-                    o[0] = acc0;
-                    o[1] = acc1;
-                    acc0 = ((runbits >> eb) & 1u) ? w[2] : acc0 + w[2];
-                    acc1 = ((runbits >> eb) & 1u) ? w[3] : acc1 + w[3];
-                    o[2] = acc0;
-                    o[3] = acc1;
-                    *reinterpret_cast<f32x4 *>(slot) = o;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // cluster t: its run's pieces, lane by lane
-                float *dst0 = up[0] ? a.R + rowpart_offset(jr[0], a.lgw, ns, k) +
-                                          (s - (jr[0] >> a.lgw) - 1) * (int64_t)k
-                                    : nullptr;
-                float *dst1 = up[1] ? a.R + rowpart_offset(jr[1], a.lgw, ns, k) +
-                                          (s - (jr[1] >> a.lgw) - 1) * (int64_t)k
-                                    : nullptr;
-                for (int t = lane; t < k; t += kWave) {
+            for (int e2 = 0; e2 < C / 2; ++e2) {
+                float *slot = stg + 2 * (lane * C) + 4 * (e2 ^ (lane & 7));
+                const f32x4 w = *reinterpret_cast<const f32x4 *>(slot);
+                const int ea = 2 * e2, eb = 2 * e2 + 1;
+                f32x4 o;
+                acc0 = ((runbits >> ea) & 1u) ? w[0] : acc0 + w[0];
+                acc1 = ((runbits >> ea) & 1u) ? w[1] : acc1 + w[1];
+                o[0] = acc0;
+                o[1] = acc1;
+                acc0 = ((runbits >> eb) & 1u) ? w[2] : acc0 + w[2];
+                acc1 = ((runbits >> eb) & 1u) ? w[3] : acc1 + w[3];
+                o[2] = acc0;
+                o[3] = acc1;
+                *reinterpret_cast<f32x4 *>(slot) = o;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // cluster t: its run's pieces, lane by lane
+            float *dst0 = up[0] ? a.R + pk_rowpart((uint32_t)jr[0], lgw, ns32, s32, k) : nullptr;
+            float *dst1 = up[1] ? a.R + pk_rowpart((uint32_t)jr[1], lgw, ns32, s32, k) : nullptr;
+            const float2 *stg2 = reinterpret_cast<const float2 *>(stg);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (kWave * h >= k) break;  // wave-uniform
+                const int t = lane + kWave * h;
+                const int32_t np = (int32_t)(pc2n[h] >> 16);
+                const float2 r0 = stg2[pc01[h] & 0xFFFFu], r1 = stg2[pc01[h] >> 16],
+                             r2 = stg2[pc2n[h] & 0xFFFFu];
+                // the pieces in chunk order (adding 0 for the missing ones)
+                float v0 = np > 0 ? r0.x : 0.f, v1 = np > 0 ? r0.y : 0.f;
+                v0 += np > 1 ? r1.x : 0.f;
+                v1 += np > 1 ? r1.y : 0.f;
+                v0 += np > 2 ? r2.x : 0.f;
+                v1 += np > 2 ? r2.y : 0.f;
+                if (np > 3) {
                     const int32_t a0 = cstart[t], a1 = cstart[t + 1];
-                    float v0 = 0.f, v1 = 0.f;
-                    if (a1 > a0)
-                        for (int32_t L0 = a0 - a0 % C; L0 < a1; L0 += C) {
-                            // the run's piece in the lane at L0
-                            const float2 pc =
-                                *reinterpret_cast<const float2 *>(stg + 2 * staged(min(a1, L0 + C) - 1));
-                            v0 += pc.x;
-                            v1 += pc.y;
-                        }
+                    for (int32_t m = 3; m < np; ++m) {
+                        const float2 r =
+                            stg2[staged(m == np - 1 ? a1 - 1 : (a0 / C + m + 1) * C - 1)];
+                        v0 += r.x;
+                        v1 += r.y;
+                    }
+                }
+                if (t < k) {
                     if (up[0]) dst0[t] = v0;
                     if (up[1]) dst1[t] = v1;
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            if constexpr (PkRow<T>::PREFETCH) {
-#pragma unroll
-                for (int r = 0; r < PK_ROWS; ++r)
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) raw[r][u] = nxt[r][u];
-            } else {
-                fetch(jn, raw);
-            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        // row indices two passes ahead (loading the row segments a pass ahead
+        // as well measured no faster)
+        int32_t pp = p + wave * PK_ROWS;
+        int32_t jc[PK_ROWS], jn[PK_ROWS], jq[PK_ROWS];
+        rows_at(pp, jc);
+        rows_at(pp + 4 * PK_ROWS, jn);
+        auto advance = [&]() {
 #pragma unroll
             for (int r = 0; r < PK_ROWS; ++r) {
                 jc[r] = jn[r];
                 jn[r] = jq[r];
             }
+            pp += 4 * PK_ROWS;
+        };
+        auto live = [&]() { return pp < seg_end && ((uint32_t)jc[0] >> lgw) <= s32; };
+        uint4 rawA[PK_ROWS][4];
+        while (live()) {
+            fetch(jc, rawA);
+            rows_at(pp + 8 * PK_ROWS, jq);
+            process(rawA, jc);
+            advance();
         }
         // flush segment (q, c): the four waves' column sums, added in wave order
         __syncthreads();  // every wave is done with its staging memory
@@ -554,6 +597,10 @@ kkm_status pk_check(const char *who, int64_t n, int32_t k, int32_t k_store, int3
     if (empty_policy != KKM_EMPTY_INF && empty_policy != KKM_EMPTY_ZERO_CENTROID) {
         set_error("%s: unknown empty-cluster policy %d", who, empty_policy);
         return KKM_ERR_ARG;
+    }
+    if (packed_strips(n, packed_lgw(k_store)) >= 65536) {  // the sweep's 32-bit offsets
+        set_error("%s: n=%lld exceeds the packed form's 65535 strips", who, (long long)n);
+        return KKM_ERR_UNSUPPORTED;
     }
     return KKM_OK;
 }
