@@ -61,15 +61,13 @@ struct PkArgs {
     const void *K;   // strip-packed
     int lgw;         // log2 of the strip width
     int64_t ns;      // strips
-    float *R;        // row-part bins: for row j, (ns - s_j - 1) x k floats, strips s_j + 1 ..
+    // row-part bins by strip and CSR position: the k sums of the row at
+    // position p over the columns of strip s at R + (s n + p) k (written for
+    // the rows left of the strip), so that the work items of a strip write
+    // their rows' sums in position order, one contiguous stretch per item
+    float *R;
+    int32_t *pos;    // CSR position of each point (the inverse of perm)
 };
-
-// First float of row j's row-part bins.
-__host__ __device__ inline int64_t rowpart_offset(int64_t j, int lgw, int64_t ns, int32_t k) {
-    const int64_t W = int64_t(1) << lgw;
-    const int64_t s = j >> lgw;
-    return (int64_t)k * (W * (s * (ns - 1) - s * (s - 1) / 2) + (j - s * W) * (ns - s - 1));
-}
 
 // Offset of row j's segment in strip s (s >= s_j) in the packed K, in
 // elements: packed_row_offset(j) + (s - s_j) W, taken with 32-bit partial
@@ -78,15 +76,6 @@ __device__ __forceinline__ int64_t pk_segment(uint32_t j, int lgw, uint32_t ns, 
     const uint32_t sj = j >> lgw, u = j - (sj << lgw);
     const uint32_t tri = sj * ns - ((sj * (sj - 1)) >> 1);
     return ((int64_t)tri << (2 * lgw)) + ((int64_t)(u * (ns - sj) + (s - sj)) << lgw);
-}
-
-// Offset of row j's k row-part sums for strip s (s > s_j), in floats:
-// rowpart_offset(j) + (s - s_j - 1) k, as above.
-__device__ __forceinline__ int64_t pk_rowpart(uint32_t j, int lgw, uint32_t ns, uint32_t s,
-                                              int32_t k) {
-    const uint32_t sj = j >> lgw, u = j - (sj << lgw);
-    const uint32_t tri = sj * (ns - 1) - ((sj * (sj - 1)) >> 1);
-    return (int64_t)k * (((int64_t)tri << lgw) + (int64_t)(u * (ns - sj - 1) + (s - sj - 1)));
 }
 
 // One work item = (strip s, chunk q of L positions in V's CSR order).
@@ -263,7 +252,7 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
             }
         };
         // one pass: the column part of the pass's rows, then their row part
-        auto process = [&](const uint4 (&raw)[PK_ROWS][4], const int32_t (&jr)[PK_ROWS]) {
+        auto process = [&](const uint4 (&raw)[PK_ROWS][4], const int32_t (&jr)[PK_ROWS], int32_t pr0) {
             bool up[PK_ROWS];
 #pragma unroll
             for (int r = 0; r < PK_ROWS; ++r) up[r] = jr[r] >= 0 && ((uint32_t)jr[r] >> lgw) < s32;
@@ -323,8 +312,8 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // cluster t: its run's pieces, lane by lane
-            float *dst0 = up[0] ? a.R + pk_rowpart((uint32_t)jr[0], lgw, ns32, s32, k) : nullptr;
-            float *dst1 = up[1] ? a.R + pk_rowpart((uint32_t)jr[1], lgw, ns32, s32, k) : nullptr;
+            float *dst0 = a.R + (s * n + pr0) * k;  // the rows at positions pr0, pr0 + 1
+            float *dst1 = dst0 + k;
             const float2 *stg2 = reinterpret_cast<const float2 *>(stg);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -376,7 +365,7 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
         while (live()) {
             fetch(jc, rawA);
             rows_at(pp + 8 * PK_ROWS, jq);
-            process(rawA, jc);
+            process(rawA, jc, pp);
             advance();
         }
         // flush segment (q, c): the four waves' column sums, added in wave order
@@ -427,6 +416,13 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
     }
 }
 
+// CSR position of every point: pos[perm[p]] = p.
+__global__ __launch_bounds__(256) void pk_positions(Inst in, int32_t *pos) {
+    if (*in.err != 0) return;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < in.n) pos[in.perm[p]] = (int32_t)p;
+}
+
 // Row part of the step: for every point i and live cluster c, the bins of
 // row i over the strips right of its own (fixed order, compensated), added
 // to the partial sum of the cluster's first slot; a workgroup per 256 points
@@ -457,14 +453,15 @@ __global__ __launch_bounds__(256) void packed_fold(PkArgs a, Inst in, const int3
         const int64_t a0 = offsets[cl], a1 = offsets[cl + 1];
         if (a1 == a0) continue;  // empty: no column has this cluster
         const int64_t si = i >> a.lgw;
-        const float *src = a.R + rowpart_offset(i, a.lgw, a.ns, k) + cl;
+        const int64_t sk = n * k;  // floats from one strip's bins to the next
+        const float *src = a.R + ((si + 1) * n + a.pos[i]) * k + cl;
         float sm = 0.f, cm = 0.f;
         const int64_t cnt = a.ns - si - 1;
         int64_t u = 0;
         for (; u + 8 <= cnt; u += 8) {  // eight loads in flight, added in order
             float v[8];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) v[b] = src[(u + b) * k];
+            for (int b = 0; b < 8; ++b) v[b] = src[(u + b) * sk];
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 float x, er;
@@ -475,7 +472,7 @@ __global__ __launch_bounds__(256) void packed_fold(PkArgs a, Inst in, const int3
         }
         for (; u < cnt; ++u) {
             float x, er;
-            two_sum(sm, src[u * k], x, er);
+            two_sum(sm, src[u * sk], x, er);
             sm = x;
             cm += er;
         }
@@ -507,6 +504,7 @@ struct PkLayout {
     int lgw;
     int64_t ns;
     size_t inst_bytes, rowpart_floats;
+    int64_t n;
 };
 
 PkLayout pk_layout(int64_t n, int32_t k, int32_t k_store) {
@@ -515,17 +513,19 @@ PkLayout pk_layout(int64_t n, int32_t k, int32_t k_store) {
     m.ns = packed_strips(n, m.lgw);
     m.g = inst_geometry(n, k, pk_chunk(n, m.ns));
     m.inst_bytes = inst_workspace_bytes(m.g);
-    m.rowpart_floats = (size_t)rowpart_offset(n, m.lgw, m.ns, k);  // rows 0 .. n-1
-    // rows of a partial last strip need no more: rowpart_offset(n) counts them all
+    m.rowpart_floats = (size_t)m.ns * (size_t)n * (size_t)k;  // by strip and position
+    m.n = n;
     return m;
 }
 
-size_t pk_carve(void *base, const PkLayout &m, void **inst, float **rowpart) {
+size_t pk_carve(void *base, const PkLayout &m, void **inst, float **rowpart, int32_t **pos) {
     Carver c(base);
     void *p = c.take<char>(m.inst_bytes);
     float *r = c.take<float>(m.rowpart_floats);
+    int32_t *q = c.take<int32_t>((size_t)m.n);
     if (inst) *inst = p;
     if (rowpart) *rowpart = r;
+    if (pos) *pos = q;
     return c.bytes();
 }
 
@@ -536,12 +536,13 @@ kkm_status pk_step(const void *K, int32_t k_store, const float *diagK, int64_t n
     const PkLayout m = pk_layout(n, k, k_store);
     void *iws = nullptr;
     float *rowpart = nullptr;
-    const size_t need = pk_carve(nullptr, m, nullptr, nullptr);
+    int32_t *pos = nullptr;
+    const size_t need = pk_carve(nullptr, m, nullptr, nullptr, nullptr);
     if (!ws || ws_bytes < need) {
         set_error("kkm_iterate_packed: workspace of %zu bytes is smaller than %zu", ws_bytes, need);
         return KKM_ERR_NOMEM;
     }
-    pk_carve(ws, m, &iws, &rowpart);
+    pk_carve(ws, m, &iws, &rowpart, &pos);
     Inst in{};
     inst_carve(iws, m.g, &in, nullptr);
     in.K = K;
@@ -560,6 +561,7 @@ kkm_status pk_step(const void *K, int32_t k_store, const float *diagK, int64_t n
     a.lgw = m.lgw;
     a.ns = m.ns;
     a.R = rowpart;
+    a.pos = pos;
     const int64_t items = m.ns * m.g.nchunk;
     if (items > 0x7fffffff) {
         set_error("kkm_iterate_packed: n=%lld needs more than 2^31 work items", (long long)n);
@@ -572,6 +574,8 @@ kkm_status pk_step(const void *K, int32_t k_store, const float *diagK, int64_t n
         else
             hipLaunchKernelGGL(packed_sweep<uint16_t>, dim3((unsigned)items), dim3(PK_THREADS), 0,
                                st, a, in, labels_in);
+        KKM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(pk_positions, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, pos);
         KKM_HIP(hipGetLastError());
         hipLaunchKernelGGL(packed_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, in,
                            labels_in);
@@ -617,7 +621,7 @@ extern "C" size_t kkm_packed_elements(int64_t n, int32_t k_store) {
 
 extern "C" size_t kkm_iterate_packed_workspace_bytes(int64_t n, int32_t k, int32_t k_store) {
     if (n < 1 || k < 1 || k > PK_MAXK || (k_store != KKM_F32 && k_store != KKM_BF16)) return 0;
-    return pk_carve(nullptr, pk_layout(n, k, k_store), nullptr, nullptr);
+    return pk_carve(nullptr, pk_layout(n, k, k_store), nullptr, nullptr, nullptr);
 }
 
 extern "C" kkm_status kkm_gram_packed(const float *X, int64_t n, int64_t d, int64_t ldx,
