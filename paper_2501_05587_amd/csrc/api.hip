@@ -445,7 +445,7 @@ extern "C" kkm_status kkm_fit_ex(const float *X, int64_t n, int64_t d, int64_t l
     FitBuffers fb;
     void *K = K_ws;
     if (!K) {
-        ldk = (n + 63) & ~int64_t(63);
+        ldk = (n + 127) & ~int64_t(127);  // rows 256-byte aligned in bfloat16 too
         const size_t kbytes = (size_t)n * (size_t)ldk * elem_bytes(k_store);
         hipError_t e = hipMalloc(&fb.K_own, kbytes);
         if (e != hipSuccess) {

@@ -77,6 +77,10 @@ __device__ __forceinline__ float kappa_from_dot(float b, float ni, float nj, int
     return b;
 }
 
+// K leaves through non-temporal stores: it is written once and not read back
+// by the kernel, so its lines should not displace the operand rows in the
+// caches (measured 80 -> 75 ms for the BF16 product with bfloat16 K at
+// n=200000, d=1024).
 template <typename OUT> struct Store;
 template <> struct Store<float> {
     static __device__ __forceinline__ float round(float v) { return v; }
@@ -85,7 +89,7 @@ template <> struct Store<float> {
     }
     static __device__ __forceinline__ void four(void *K, int64_t idx, const float v[4]) {
         f32x4 w = {v[0], v[1], v[2], v[3]};
-        *reinterpret_cast<f32x4 *>(static_cast<float *>(K) + idx) = w;
+        __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(static_cast<float *>(K) + idx));
     }
 };
 template <> struct Store<uint16_t> {
@@ -96,8 +100,9 @@ template <> struct Store<uint16_t> {
     static __device__ __forceinline__ void four(void *K, int64_t idx, const float v[4]) {
         typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
         const f32x4 f = {v[0], v[1], v[2], v[3]};
-        *reinterpret_cast<bf16x4 *>(static_cast<uint16_t *>(K) + idx) =
-            __builtin_convertvector(f, bf16x4);
+        const bf16x4 b = __builtin_convertvector(f, bf16x4);
+        __builtin_nontemporal_store(__builtin_bit_cast(uint64_t, b),
+                                    reinterpret_cast<uint64_t *>(static_cast<uint16_t *>(K) + idx));
     }
 };
 
