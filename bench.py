@@ -4,17 +4,22 @@
 Workload: a 64-component Gaussian mixture in R^1024 (means N(0,1), sigma 0.5),
 Gaussian kernel gamma = 1/1024, random initial labels.
 
-Plain FP32 leg (the timed steps).  One step = one complete run of the method
+Plain FP32 legs (the timed steps).  One step = one complete run of the method
 on the resident input: the Gram kernel K = kappa(X X^T) (FP32 MFMA, K stored
-FP32, 160 GB) followed by 30 reassignment steps (V in CSR form, SpMM row sweep
-of K, centroid norms, fused distance/argmin/histogram) and the FP64 objective
-of the final labels: the paper's protocol of exactly 30 iterations.
+FP32) followed by 30 reassignment steps (V in CSR form, the sweep of K,
+centroid norms, fused distance/argmin/histogram) and the FP64 objective of the
+final labels: the paper's protocol of exactly 30 iterations.  Two layouts of
+the same FP32 K: the strip-packed upper triangle (81 GB; each stored entry
+read once per step and fed to both sides of the sum; the headline) and the
+dense n x ldk matrix (160 GB; the SpMM row sweep).
 `value` = iterations per second = 1 / the median time of one reassignment step
-over iterations 2..30 of the timed runs (HIP events on the launching stream;
-the Gram excluded); the rate with the Gram included is its own field.
+on the strip-packed K over iterations 2..30 of the timed runs (HIP events on
+the launching stream; the Gram excluded); the rate with the Gram included and
+the dense-K figures are their own fields.
 
 Also reported:
-* time-to-converge of the plain FP32 form from the random labels;
+* time-to-converge of the plain FP32 form from the random labels (packed and
+  dense K);
 * the mixed + learned form: BF16 Gram with K stored BF16 (80 GB), a feature
   network trained beforehand on 10^7 kernel-value pairs of the same mixture
   (training time reported separately), the warm start (k-means++ and Lloyd in
@@ -27,8 +32,10 @@ Also reported:
   error report (max distance error, objective error, label flips);
 * the MNIST-shaped workload (n=60000, d=784, polynomial kernel, 30 iterations)
   and the rings workload (n=1000): Gram and sweep rooflines, time per step;
-* roofline positions of the sweep (HBM) and the Gram (MFMA) from HIP-event
-  timings of those launches, and HBM traffic from the recorded counters;
+* roofline positions of the packed sweep (HBM; its algorithmic bytes are the
+  packed entries plus the row-part sums it writes), the dense sweep and the
+  Gram (MFMA) from HIP-event timings of those launches, and HBM traffic from
+  the recorded counters;
 * the matrix-free step (no stored K) beside the stored-K step at n=100000,
   k=32, d in {32, 64, 128, 256}, BF16 product;
 * the FP64 oracle timed on the host on the first 20000 points (K build and
@@ -87,7 +94,9 @@ def sources_sha(paths):
 
 
 def traffic_bytes(kernel, n):
-    t = TRAFFIC[kernel]
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
     if t["n"] != n or sources_sha(t["sources"]) != t["sha256"]:
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
@@ -186,6 +195,13 @@ def cpu_baseline(w, rows, iters, full=False):
     log("oracle on %d points: K %.2f s, %.2f ms per iteration (%d threads), %.1f ms per iteration "
         "(1 thread)" % (rows, kb, loop / iters * 1e3, nthr, rec1["loop_ms_per_iter"]))
     return rec, K
+
+
+def rowpart_bytes(n, k, W):
+    """Bytes of the row-part sums a packed sweep writes: k floats for every
+    row and every strip right of the row's own."""
+    ns = (n + W - 1) // W
+    return float(sum(min(W, n - s * W) * (ns - s - 1) for s in range(ns))) * k * 4
 
 
 def iter_spans(kkm, runs, per_run):
@@ -536,8 +552,9 @@ def packed_leg(kkm, torch, dev, iters=30, reps=2):
     entry read once per step) beside the dense K on the benchmark workload
     (n=200000, d=1024, k=64): FP32 and bfloat16 storage, 30 fixed iterations
     from the random labels.  Per form: the median step (iterations 2..30), the
-    packed sweep (both parts and the fold of the row part) against the bytes
-    it must read (the packed entries: about n^2/2 s_K), and the Gram writing
+    packed sweep kernel (both parts) against the bytes it must move (the packed
+    entries, about n^2/2 s_K, plus the row-part sums it writes), the fold of
+    the row part, and the Gram writing
     the packed K; and to convergence from the random labels (FP32) and from
     nothing else."""
     import numpy as np
@@ -568,21 +585,24 @@ def packed_leg(kkm, torch, dev, iters=30, reps=2):
         torch.cuda.synchronize()
         its = iter_spans(kkm, reps, iters + 1)
         sw = float(np.median(kkm.kkm_timing_spans("sweep")))
+        fold = float(np.median(kkm.kkm_timing_spans("fold")))
         gram = float(np.median(kkm.kkm_timing_spans("gram")))
         kkm.kkm_timing_enable(False)
         pbytes = float(kkm.packed_elements(n, ks)) * eb
+        rpb = rowpart_bytes(n, w.k, 1024 if ks == kkm.F32 else 2048)
         med = float(np.median(its))
-        rec = {"k_store": name, "packed_bytes": pbytes, "dense_bytes": float(n) * n * eb,
-               "iter_ms": med, "iters_per_s": 1e3 / med, "sweep_ms": sw,
-               "sweep_gbs_packed_bytes": pbytes / (sw * 1e-3) / 1e9,
-               "sweep_frac_hbm": pbytes / (sw * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        rec = {"k_store": name, "packed_bytes": pbytes, "rowpart_bytes": rpb,
+               "dense_bytes": float(n) * n * eb, "iter_ms": med, "iters_per_s": 1e3 / med,
+               "sweep_ms": sw, "fold_ms": fold,
+               "sweep_gbs": (pbytes + rpb) / (sw * 1e-3) / 1e9,
+               "sweep_frac_hbm": (pbytes + rpb) / (sw * 1e-3) / 1e9 / HBM_PEAK_GBS,
                "gram_ms": gram, "objective_30": r["objective"]}
         if ks == kkm.F32:
             cs, rc = timed_runs(torch, lambda: run(300, True), reps=1)
             rec["to_convergence"] = {"seconds": cs, "iters": rc["iters"], "objective": rc["objective"]}
         log("packed %s: step %.3f ms (%.1f iters/s), sweep %.3f ms = %.0f GB/s on %.1f GB (%.3f of HBM), "
-            "gram %.1f ms" % (name, med, 1e3 / med, sw, rec["sweep_gbs_packed_bytes"], pbytes / 1e9,
-                              rec["sweep_frac_hbm"], gram))
+            "fold %.3f ms, gram %.1f ms" % (name, med, 1e3 / med, sw, rec["sweep_gbs"],
+                                            (pbytes + rpb) / 1e9, rec["sweep_frac_hbm"], fold, gram))
         out[name] = rec
         del Kp
         torch.cuda.empty_cache()
@@ -948,9 +968,70 @@ def main():
               "unit": "TFLOP/s", "traffic": traffic_bytes("gram_f32_mfma", n),
               "algorithmic_flops": gram_flops, "avg_ms": gram_launch_ms, "launches": tim["gram"][1]}
     roof_g["frac"] = roof_g["achieved"] / roof_g["peak"]
+    dense = {"iter_ms": iter_ms, "iters_per_s": 1e3 / iter_ms, "gram_ms": gram_ms,
+             "ms_per_step": wall / args.steps * 1e3, "iters_per_s_incl_gram": total_iters / wall,
+             "k_store": "f32 [n, ldk] row-major, both triangles", "roofline": roof}
 
-    # ------------------------------------------------------------ plain FP32 to convergence
+    # ------------------------------------------------------------ plain FP32, strip-packed K (headline)
+    # K's upper triangle stored once in strips of 1024 columns; each stored
+    # entry is read once per step and feeds both sides of the sum
+    Kp = kkm.alloc_packed_kernel_matrix(n, kkm.F32, dev)
+
+    def pstep(max_iter=iters, conv=False):
+        return kkm.kkm_fit_packed(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.F32, k_store=kkm.F32,
+                                  max_iter=max_iter, check_convergence=conv, K_ws=Kp, labels_out=lab)
+
+    for i in range(args.warmup):
+        pstep()
+    torch.cuda.synchronize()
+    kkm.kkm_timing_enable(True)
+    t0 = time.perf_counter()
+    prs = []
+    for i in range(args.steps):
+        prs.append(pstep())
+        log("packed step %d done: gram %.1f ms, %d steps %.1f ms" % (i, prs[-1]["times_ms"][0],
+                                                                  prs[-1]["iters"], prs[-1]["times_ms"][1]))
+    torch.cuda.synchronize()
+    pwall = time.perf_counter() - t0
+    p_iter_ms = float(np.median(iter_spans(kkm, args.steps, iters + 1)))
+    p_sweep = kkm.kkm_timing_spans("sweep")
+    p_fold = kkm.kkm_timing_spans("fold")
+    p_gram = kkm.kkm_timing_spans("gram")
+    kkm.kkm_timing_enable(False)
+    p_sweep_ms = float(np.mean(p_sweep))
+    pbytes = float(kkm.packed_elements(n, kkm.F32)) * 4
+    rp_bytes = rowpart_bytes(n, w.k, 1024)
+    roof = {"bound": "hbm", "kernel": "packed_sweep<float>",
+            "achieved": (pbytes + rp_bytes) / (p_sweep_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "traffic": traffic_bytes("packed_sweep", n),
+            "algorithmic_bytes": pbytes + rp_bytes, "packed_k_bytes": pbytes, "rowpart_bytes": rp_bytes,
+            "avg_ms": p_sweep_ms, "launches": int(p_sweep.size)}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    packed = {"iter_ms": p_iter_ms, "iters_per_s": 1e3 / p_iter_ms,
+              "gram_ms": float(np.mean(p_gram)), "sweep_ms": p_sweep_ms,
+              "fold_ms": float(np.mean(p_fold)), "ms_per_step": pwall / args.steps * 1e3,
+              "iters_per_s_incl_gram": sum(r["iters"] for r in prs) / pwall,
+              "objective_30": prs[-1]["objective"]}
+    log("packed FP32: %.3f ms per iteration (sweep %.3f ms = %.0f GB/s, fold %.3f ms), gram %.1f ms"
+        % (p_iter_ms, p_sweep_ms, roof["achieved"], packed["fold_ms"], packed["gram_ms"]))
     plain = None
+    if not args.no_converge:
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        rc = pstep(300, True)
+        torch.cuda.synchronize()
+        labs = lab.cpu().numpy()
+        plain = {"k_store": "f32 strip-packed", "seconds": time.perf_counter() - tc, "iters": rc["iters"],
+                 "objective": rc["objective"], "gram_ms": rc["times_ms"][0],
+                 "iter_ms": rc["times_ms"][1] / max(rc["iters"], 1), "ari_vs_truth": ari(labs, truth),
+                 "empty_clusters": int((np.bincount(labs, minlength=w.k) == 0).sum())}
+        log("plain (packed K) converged: %d iterations in %.3f s, J=%.6f" % (rc["iters"], plain["seconds"],
+                                                                            rc["objective"]))
+    del Kp
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ plain FP32 to convergence, dense K
+    plain_dense = None
     if not args.no_converge:
         torch.cuda.synchronize()
         tc = time.perf_counter()
@@ -958,12 +1039,12 @@ def main():
                             check_convergence=True, K_ws=K, labels_out=lab)
         torch.cuda.synchronize()
         labs = lab.cpu().numpy()
-        plain = {"seconds": time.perf_counter() - tc, "iters": rc["iters"], "objective": rc["objective"],
-                 "gram_ms": rc["times_ms"][0], "iter_ms": rc["times_ms"][1] / max(rc["iters"], 1),
-                 "ari_vs_truth": ari(labs, truth),
-                 "empty_clusters": int((np.bincount(labs, minlength=w.k) == 0).sum())}
-        log("plain converged: %d iterations in %.3f s, J=%.6f" % (rc["iters"], plain["seconds"],
-                                                                  rc["objective"]))
+        plain_dense = {"k_store": "f32 dense", "seconds": time.perf_counter() - tc, "iters": rc["iters"],
+                       "objective": rc["objective"], "gram_ms": rc["times_ms"][0],
+                       "iter_ms": rc["times_ms"][1] / max(rc["iters"], 1), "ari_vs_truth": ari(labs, truth),
+                       "empty_clusters": int((np.bincount(labs, minlength=w.k) == 0).sum())}
+        log("plain (dense K) converged: %d iterations in %.3f s, J=%.6f" % (rc["iters"], plain_dense["seconds"],
+                                                                            rc["objective"]))
 
     # ------------------------------------------------------------ mixed + learned
     learned = None
@@ -1042,7 +1123,9 @@ def main():
             "bf16_random_start": {"seconds": control_s, "iters": rcn["iters"],
                                   "objective": rcn["objective"],
                                   "ari_vs_truth": ari(control_labels, truth)},
-            "exact_iters_saved_fp32": (plain["iters"] - ref["iters"]) if plain else None,
+            # the reference ran on the dense K, so the iterations saved are taken against
+            # the plain run on the same dense K
+            "exact_iters_saved_fp32": (plain_dense["iters"] - ref["iters"]) if plain_dense else None,
             "exact_iters_saved_bf16": rcn["iters"] - r["iters"],
             "sweep_bf16": {"avg_ms": sw16, "achieved_gbs": float(n) * n * 2 / (sw16 * 1e-3) / 1e9,
                            "frac_hbm": float(n) * n * 2 / (sw16 * 1e-3) / 1e9 / HBM_PEAK_GBS},
@@ -1052,8 +1135,11 @@ def main():
             "kernel_kmeanspp_warm_start": kseeded,
         }
         if plain:
+            # against the faster plain FP32 run (strip-packed K); the dense-K run beside it
             learned["speedup_time_to_converge"] = speedups(plain["seconds"], control_s, secs,
                                                            train_rep["seconds"])
+        if plain_dense:
+            learned["speedup_vs_plain_fp32_dense_k"] = plain_dense["seconds"] / secs
         log("mixed+learned: %.3f s (warm start %.3f s, %d cheap + %d exact iterations), ARI vs FP32 "
             "from same start %.4f; bf16 from random labels %.3f s (%d iterations)" % (
                 secs, ws_s, ch, r["iters"], learned["ari_vs_fp32_from_same_warm_start"], control_s,
@@ -1083,12 +1169,12 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": 1e3 / iter_ms,
+        "value": 1e3 / p_iter_ms,
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": pwall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -1096,14 +1182,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "gmm200k: %d-component Gaussian mixture, sigma 0.5" % w.k,
                    "n": n, "d": w.d, "k": w.k, "kernel": "gaussian gamma=1/%d" % w.d,
-                   "iterations_per_step": iters, "gram": "f32 mfma", "k_store": "f32",
+                   "iterations_per_step": iters, "gram": "f32 mfma",
+                   "k_store": "f32, strip-packed upper triangle (strips of 1024 columns)",
                    "parallelism": "single gpu"},
-        "value_definition": "1 / median time of one reassignment step, iterations 2..%d of the "
-                            "timed runs, Gram excluded" % iters,
-        "iters_per_s_incl_gram": total_iters / wall,
-        "gram_ms": gram_ms,
-        "iter_ms": iter_ms,
+        "value_definition": "1 / median time of one reassignment step on the strip-packed FP32 K, "
+                            "iterations 2..%d of the timed runs, Gram excluded" % iters,
+        "iters_per_s_incl_gram": packed["iters_per_s_incl_gram"],
+        "gram_ms": packed["gram_ms"],
+        "iter_ms": p_iter_ms,
+        "packed_fp32": packed,
+        "dense_fp32": dense,
         "plain_fp32_to_convergence": plain,
+        "plain_fp32_dense_to_convergence": plain_dense,
         "mixed_learned_to_convergence": learned,
         "metric_form_vs_oracle_20k": metric_20k,
         "mnist_like_60k": small and small["mnist_like"],

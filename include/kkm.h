@@ -543,17 +543,19 @@ kkm_status kkm_fit_packed(const float *X, int64_t n, int64_t d, int64_t ldx, int
 /*
  * Launch timing for benchmarks (process-wide).  kkm_timing_enable(1) clears
  * the records and starts bracketing every Gram launch, every SpMM sweep launch
- * and every whole kkm_iterate step with HIP events on the caller's stream;
- * kkm_timing_enable(0) clears and stops.  kkm_timing_read waits for the
- * recorded events and returns, per class {0: Gram, 1: sweep, 2: iterate step},
- * the total milliseconds (host double[3]) and the number of launches (host
- * int64[3]) since timing was enabled.
+ * (for a strip-packed K the sweep kernel alone), every fold of the packed row
+ * part and every whole kkm_iterate step with HIP events on the caller's
+ * stream; kkm_timing_enable(0) clears and stops.  kkm_timing_read waits for
+ * the recorded events and returns, per class {0: Gram, 1: sweep, 2: iterate
+ * step, 3: packed fold}, the total milliseconds (host double[4]) and the
+ * number of launches (host int64[4]) since timing was enabled.
  */
 kkm_status kkm_timing_enable(int32_t on);
 kkm_status kkm_timing_read(double *total_ms, int64_t *launches);
 
 /* kkm_timing_spans — the individual durations (milliseconds, launch order) of
- * the launches of class cls (0: Gram, 1: sweep, 2: iterate step) recorded since
+ * the launches of class cls (0: Gram, 1: sweep, 2: iterate step, 3: packed
+ * fold) recorded since
  * timing was enabled: ms (host double [cap]) receives the first min(cap,
  * *count) of them and *count (host) their number.  Waits for the recorded
  * events.  KKM_ERR_ARG for an unknown class or a NULL output. */

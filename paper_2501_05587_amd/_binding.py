@@ -669,21 +669,21 @@ def kkm_timing_enable(on: bool = True):
 
 
 def kkm_timing_read():
-    """{'gram'|'sweep'|'iterate': (total_ms, launches)} since timing was enabled."""
+    """{'gram'|'sweep'|'iterate'|'fold': (total_ms, launches)} since timing was enabled."""
     import numpy as np
-    ms = np.zeros(3, dtype=np.float64)
-    cnt = np.zeros(3, dtype=np.int64)
+    ms = np.zeros(4, dtype=np.float64)
+    cnt = np.zeros(4, dtype=np.int64)
     _check(lib().kkm_timing_read(ms.ctypes.data_as(_vp), cnt.ctypes.data_as(_vp)))
     return {"gram": (float(ms[0]), int(cnt[0])), "sweep": (float(ms[1]), int(cnt[1])),
-            "iterate": (float(ms[2]), int(cnt[2]))}
+            "iterate": (float(ms[2]), int(cnt[2])), "fold": (float(ms[3]), int(cnt[3]))}
 
 
-_TIMING_CLASS = {"gram": 0, "sweep": 1, "iterate": 2}
+_TIMING_CLASS = {"gram": 0, "sweep": 1, "iterate": 2, "fold": 3}
 
 
 def kkm_timing_spans(cls):
     """Durations in ms (numpy float64, launch order) of the recorded launches of
-    class 'gram', 'sweep' or 'iterate' since timing was enabled."""
+    class 'gram', 'sweep', 'iterate' or 'fold' since timing was enabled."""
     import numpy as np
     c = _TIMING_CLASS[cls]
     cnt = _i64()

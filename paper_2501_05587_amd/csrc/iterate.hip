@@ -774,9 +774,7 @@ kkm_status step_launch_custom(const Inst &in, const int32_t *labels_in, int32_t 
     hipLaunchKernelGGL(v_scatter<false>, dim3((unsigned)in.nblk), pb,
                        (size_t)(k + 1 + 4 * k) * sizeof(int32_t), stream, s, labels_in);
     KKM_HIP(hipGetLastError());
-    const TimedSpan span = timing_begin(TK_SWEEP, stream);
-    KKM_TRY(sweep(stream));
-    timing_end(span, stream);
+    KKM_TRY(sweep(stream));  // times its own launches
     hipLaunchKernelGGL((centroid_norms<4, false>), dim3((unsigned)k), dim3(256), 0, stream, s);
     KKM_HIP(hipGetLastError());
     hipLaunchKernelGGL(assign_fused<false>, dim3((unsigned)in.nblk), pb,

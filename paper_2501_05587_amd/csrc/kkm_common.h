@@ -37,7 +37,7 @@ kkm_status hip_fail(hipError_t e, const char *what);
 // When enabled (kkm_timing_enable), HIP events bracket the Gram and sweep
 // launches on their stream; kkm_timing_read turns them into totals.
 
-enum TimedKernel { TK_GRAM = 0, TK_SWEEP = 1, TK_ITERATE = 2, TK_COUNT = 3 };
+enum TimedKernel { TK_GRAM = 0, TK_SWEEP = 1, TK_ITERATE = 2, TK_FOLD = 3, TK_COUNT = 4 };
 
 struct TimedSpan {
     hipEvent_t start = nullptr, stop = nullptr;

@@ -529,6 +529,7 @@ kkm_status mf_step(const MfArgs &a, int32_t gram_prec, const MfLayout &m, const 
     }
     auto sweep = [&](hipStream_t st) -> kkm_status {
         const dim3 grid((unsigned)items), blk(256);
+        const TimedSpan span = timing_begin(TK_SWEEP, st);
         if (gram_prec == KKM_F32)
             hipLaunchKernelGGL(matfree_sweep<KKM_F32>, grid, blk, 0, st, a, in, labels_in);
         else if (gram_prec == KKM_BF16)
@@ -536,6 +537,7 @@ kkm_status mf_step(const MfArgs &a, int32_t gram_prec, const MfLayout &m, const 
         else
             hipLaunchKernelGGL(matfree_sweep<KKM_FP8_ROWSCALED>, grid, blk, 0, st, a, in, labels_in);
         KKM_HIP(hipGetLastError());
+        timing_end(span, st);
         return KKM_OK;
     };
     (void)k;

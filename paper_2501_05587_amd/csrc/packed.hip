@@ -568,6 +568,7 @@ kkm_status pk_step(const void *K, int32_t k_store, const float *diagK, int64_t n
         return KKM_ERR_UNSUPPORTED;
     }
     auto sweep = [&](hipStream_t st) -> kkm_status {
+        const TimedSpan span = timing_begin(TK_SWEEP, st);
         if (k_store == KKM_F32)
             hipLaunchKernelGGL(packed_sweep<float>, dim3((unsigned)items), dim3(PK_THREADS), 0, st,
                                a, in, labels_in);
@@ -575,11 +576,14 @@ kkm_status pk_step(const void *K, int32_t k_store, const float *diagK, int64_t n
             hipLaunchKernelGGL(packed_sweep<uint16_t>, dim3((unsigned)items), dim3(PK_THREADS), 0,
                                st, a, in, labels_in);
         KKM_HIP(hipGetLastError());
+        timing_end(span, st);
+        const TimedSpan fold = timing_begin(TK_FOLD, st);
         hipLaunchKernelGGL(pk_positions, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, pos);
         KKM_HIP(hipGetLastError());
         hipLaunchKernelGGL(packed_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, in,
                            labels_in);
         KKM_HIP(hipGetLastError());
+        timing_end(fold, st);
         return KKM_OK;
     };
     return step_launch_custom(in, labels_in, labels_out, sweep, stream);

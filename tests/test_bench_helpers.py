@@ -46,3 +46,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_rowpart_bytes_closed_form():
+    # whole strips: every row of strip s has ns - s - 1 strips to its right,
+    # W k 4 (0 + 1 + ... + ns - 1) bytes in all
+    W, k = 1024, 64
+    for ns in (1, 2, 7, 196):
+        n = ns * W
+        assert bench.rowpart_bytes(n, k, W) == W * k * 4 * ns * (ns - 1) // 2
+    # a ragged last strip: its rows have no strip to their right
+    assert bench.rowpart_bytes(3 * W - 5, k, W) == bench.rowpart_bytes(3 * W, k, W)
+    assert bench.rowpart_bytes(1, 3, W) == 0.0
+
+
+def test_traffic_of_an_unrecorded_kernel_is_null():
+    assert bench.traffic_bytes("no_such_kernel", 200000) is None
