@@ -67,15 +67,21 @@ BF16_MFMA_PEAK_TFS = 2500.0
 # WRITE_SIZE all of them).  Valid only while the kernel's sources hash to the
 # recorded value; otherwise the traffic is reported as null.
 TRAFFIC = {
+    "packed_sweep": {"sources": ["csrc/packed.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
+                     "sha256": "3dd81dcb6d8c76e60040fcf089b91fca8e89d0a077994d437035d7fab94d11ce",
+                     "n": 200000, "fetch_kib": 39630000.0, "write_kib": 4981000.0,
+                     "fetch_scale": 1.9999, "write_scale": 1.0},
     "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
-                       "sha256": "e41ef9ea21834fec006f837abf498909ed9c90ff1eadf490973f6ce25bd01c1f",
+                       "sha256": "5144509e16a16636ce2b3fd0a1c8369bef350864dc390967a6a6a465951e62dc",
                        "n": 200000, "fetch_kib": 78170000.0, "write_kib": 89550.0,
                        "fetch_scale": 1.9999, "write_scale": 1.0},
-    "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_f32.hip", "csrc/gram_tile.h", "csrc/kkm_common.h"],
-                      "sha256": "7e989430ed7304f47b79b1469f4612f63795ab2f06251711c884852291d5bee2",
-                      "n": 200000, "fetch_kib": 152000000.0, "write_kib": 156300000.0,
+    "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_f32.hip", "csrc/gram_tile.h",
+                                  "csrc/kkm_common.h"],
+                      "sha256": "7b766ecfcd9198c14ac729c43d4c00644e90efa8b0e7ee4356a215007a00c917",
+                      "n": 200000, "fetch_kib": 147900000.0, "write_kib": 156300000.0,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }
+
 
 # feature network and its training (learned warm start)
 H1, H2, OUT = 512, 512, 256
