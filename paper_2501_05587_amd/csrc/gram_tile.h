@@ -114,8 +114,10 @@ constexpr size_t epi_lds_bytes(int halves) { return sizeof(float) * (GM / halves
 
 // Rows r = 0..ROWS-1 of the staged tile T to K[row0 + r][col0 .. col0 + 127],
 // skipping rows and columns at or past n: each thread stores 4 columns of
-// every eighth row, reading eight rows from LDS before it waits.
-template <typename OUT, int ROWS = GM>
+// every eighth row, reading B rows from LDS before it waits (B = 4 when half
+// a tile is staged: the half-tile epilogue keeps its accumulators live across
+// the passes, and eight rows in flight made it spill registers to memory).
+template <typename OUT, int ROWS = GM, int B = (ROWS == GM ? 8 : 4)>
 __device__ __forceinline__ void store_rows(const Epi &e, const float *T, int64_t row0, int64_t col0) {
     const int tid = threadIdx.x;
     const int c4 = (tid & 31) * 4;
@@ -123,14 +125,14 @@ __device__ __forceinline__ void store_rows(const Epi &e, const float *T, int64_t
     if (gj0 >= e.n) return;
     const bool vec = e.vec_k && gj0 + 3 < e.n;
 #pragma unroll
-    for (int h = 0; h < ROWS / 64; ++h) {
-        f32x4 w[8];
+    for (int h = 0; h < ROWS / (8 * B); ++h) {
+        f32x4 w[B];
 #pragma unroll
-        for (int it = 0; it < 8; ++it)
-            w[it] = *reinterpret_cast<const f32x4 *>(T + ((tid >> 5) + 8 * (8 * h + it)) * TS + c4);
+        for (int it = 0; it < B; ++it)
+            w[it] = *reinterpret_cast<const f32x4 *>(T + ((tid >> 5) + 8 * (B * h + it)) * TS + c4);
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-            const int64_t gi = row0 + (tid >> 5) + 8 * (8 * h + it);
+        for (int it = 0; it < B; ++it) {
+            const int64_t gi = row0 + (tid >> 5) + 8 * (B * h + it);
             if (gi >= e.n) continue;
             const float v[4] = {w[it][0], w[it][1], w[it][2], w[it][3]};
             const int64_t idx = k_index(e, gi, gj0);
@@ -317,6 +319,33 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
                         }
                     }
                 }
+            // bfloat16 K: the values are rounded to bfloat16 here (the stores round
+            // them anyway, and rounding an exact bfloat16 value again changes no bit)
+            // and kept two per register through the passes below; with the FP32
+            // accumulators live across them the kernel spilled registers to memory
+            constexpr bool PACK = sizeof(OUT) == 2;
+            uint32_t kb[2][2][PACK ? 8 : 1];
+            if constexpr (PACK) {
+                typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+                typedef float f32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) {
+                            const f32x2 f = {acc[mi][ni][2 * t], acc[mi][ni][2 * t + 1]};
+                            kb[mi][ni][t] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
+                        }
+            }
+            auto kept = [&](int mi, int ni, int idx) -> float {
+                if constexpr (PACK) {
+                    const uint32_t w = kb[mi][ni][idx >> 1];
+                    return __uint_as_float((idx & 1) ? (w & 0xFFFF0000u) : (w << 16));
+                } else {
+                    return acc[mi][ni][idx];
+                }
+            };
             // transposed, RH columns at a time (in halves: the waves with wc == h
             // hold them): T[jj - RH h][ii], then rows K[n0 + jj][m0 ..]; off the
             // diagonal m0 + 127 < n0
@@ -332,8 +361,8 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
 #pragma unroll
                             for (int rg = 0; rg < 4; ++rg) {
                                 const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
-                                const f32x4 w = {acc[mi][ni][4 * rg], acc[mi][ni][4 * rg + 1],
-                                                 acc[mi][ni][4 * rg + 2], acc[mi][ni][4 * rg + 3]};
+                                const f32x4 w = {kept(mi, ni, 4 * rg), kept(mi, ni, 4 * rg + 1),
+                                                 kept(mi, ni, 4 * rg + 2), kept(mi, ni, 4 * rg + 3)};
                                 *reinterpret_cast<f32x4 *>(T + jl * TS + ii0) = w;
                             }
                         }
@@ -356,7 +385,7 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
                                 const int il0 = wr * 64 + mi * 32 + 8 * rg + 4 * half - RH * h;
 #pragma unroll
                                 for (int r = 0; r < 4; ++r)
-                                    T[(il0 + r) * TS + jj] = acc[mi][ni][4 * rg + r];
+                                    T[(il0 + r) * TS + jj] = kept(mi, ni, 4 * rg + r);
                             }
                         }
                 }
@@ -682,17 +711,29 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
     const int ld_row = tid >> 3;          // 8 threads x 16 bytes per row slab
     const int ld_col = (tid & 7) * 16;
 
+    // The tile's two row blocks as buffer ranges over their rows that exist
+    // (a load past the range reads zeros, so rows at or past n need no
+    // test): one 32-bit lane offset per row group, shared by both operands,
+    // and the slab offset in a scalar register.
+    const int64_t ra_rows = min((int64_t)GM, a.e.n - m0), rb_rows = min((int64_t)GM, a.e.n - n0);
+    const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<unsigned char *>(a.Xq + m0 * a.ldq_bytes), (short)0, (int)(ra_rows * a.ldq_bytes),
+        0x00020000);
+    const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<unsigned char *>(a.Xq + n0 * a.ldq_bytes), (short)0, (int)(rb_rows * a.ldq_bytes),
+        0x00020000);
+    uint32_t voff[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) voff[u] = (uint32_t)((ld_row + 32 * u) * a.ldq_bytes + ld_col);
     uint4 ra[4], rb[4];
     auto gload = [&](int64_t slab) {
+        const int soff = (int)(slab * SLAB);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int64_t r1 = m0 + ld_row + 32 * u, r2 = n0 + ld_row + 32 * u;
-            ra[u] = make_uint4(0, 0, 0, 0);
-            rb[u] = make_uint4(0, 0, 0, 0);
-            if (r1 < a.e.n)
-                ra[u] = *reinterpret_cast<const uint4 *>(a.Xq + r1 * a.ldq_bytes + slab * SLAB + ld_col);
-            if (r2 < a.e.n)
-                rb[u] = *reinterpret_cast<const uint4 *>(a.Xq + r2 * a.ldq_bytes + slab * SLAB + ld_col);
+            const auto x = __builtin_amdgcn_raw_buffer_load_b128(rsa, voff[u], soff, 0);
+            const auto y = __builtin_amdgcn_raw_buffer_load_b128(rsb, voff[u], soff, 0);
+            ra[u] = make_uint4(x[0], x[1], x[2], x[3]);
+            rb[u] = make_uint4(y[0], y[1], y[2], y[3]);
         }
     };
     auto sstore = [&](int buf) {
