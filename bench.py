@@ -595,7 +595,7 @@ def packed_leg(kkm, torch, dev, iters=30, reps=2):
         gram = float(np.median(kkm.kkm_timing_spans("gram")))
         kkm.kkm_timing_enable(False)
         pbytes = float(kkm.packed_elements(n, ks)) * eb
-        rpb = rowpart_bytes(n, w.k, 1024 if ks == kkm.F32 else 2048)
+        rpb = rowpart_bytes(n, w.k, 1024)
         med = float(np.median(its))
         rec = {"k_store": name, "packed_bytes": pbytes, "rowpart_bytes": rpb,
                "dense_bytes": float(n) * n * eb, "iter_ms": med, "iters_per_s": 1e3 / med,

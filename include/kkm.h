@@ -502,7 +502,7 @@ kkm_status kkm_fit_matfree(const float *X, int64_t n, int64_t d, int64_t ldx, in
 /*
  * The strip-packed symmetric K (Sec. 4.2 names packed triangular storage as
  * what a SYRK-built K needs; Sec. 4.3 streams K every iteration): the upper
- * triangle in strips of W columns (W = 1024 for FP32, 2048 for bfloat16).
+ * triangle in strips of W = 1024 columns (FP32 or bfloat16).
  * Row i, in strip s_i = i / W, stores its columns [s_i W, ns W) contiguously,
  * ns = ceil(n / W): the diagonal W x W block of each strip whole, every block
  * right of it once, about n^2 / 2 entries.  Rows follow each other with no

@@ -101,8 +101,11 @@ inline int64_t packed_elements(int64_t n, int lgw) {
     const int64_t W = int64_t(1) << lgw, ns = packed_strips(n, lgw);
     return W * W * ns * (ns + 1) / 2;
 }
-// Strip width of the packed layout for K stored as FP32 (1024) or bfloat16 (2048).
-inline int packed_lgw(int32_t k_store) { return k_store == KKM_BF16 ? 11 : 10; }
+// Strip width of the packed layout: 1024 columns for K stored FP32 or bfloat16.
+inline int packed_lgw(int32_t k_store) {
+    (void)k_store;
+    return 10;
+}
 
 // ---------------------------------------------------------------- workspace carving
 

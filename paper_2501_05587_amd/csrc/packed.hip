@@ -34,6 +34,7 @@ constexpr int PK_MAXK = 128;          // bins per row
 template <typename T> struct PkRow;
 template <> struct PkRow<float> {
     static constexpr int E = 4;     // elements per 16-byte load
+    static constexpr int LOADS = 4; // 16-byte loads per lane and row: 16 columns
     static constexpr int ROWS = 2;  // rows per wave pass (4: two waves per SIMD instead of three, slower)
     static constexpr int BLOCKS = 3;  // workgroups per CU (VGPR budget)
     static __device__ __forceinline__ void unpack(const uint4 &w, float (&v)[E]) {
@@ -45,8 +46,12 @@ template <> struct PkRow<float> {
 };
 template <> struct PkRow<uint16_t> {
     static constexpr int E = 8;
+    // two 16-byte loads per lane and row: the same 16 columns per lane and
+    // 1024-column strips as FP32 (32 columns per lane held the kernel's
+    // registers past 256 and spilled them to memory)
+    static constexpr int LOADS = 2;
     static constexpr int ROWS = 2;
-    static constexpr int BLOCKS = 2;
+    static constexpr int BLOCKS = 3;
     static __device__ __forceinline__ void unpack(const uint4 &w, float (&v)[E]) {
         const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -90,8 +95,9 @@ template <typename T>
 __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkArgs a, Inst in,
                                                            const int32_t *labels) {
     constexpr int E = PkRow<T>::E;
-    constexpr int C = 4 * E;        // columns per lane
-    constexpr int W = kWave * C;    // strip width (1024 FP32, 2048 bfloat16)
+    constexpr int NL = PkRow<T>::LOADS;  // 16-byte loads per lane and row
+    constexpr int C = NL * E;       // columns per lane
+    constexpr int W = kWave * C;    // strip width: 1024 columns
     constexpr int G = W / 256;      // 256-column groups of the own-cluster sums
     constexpr int PK_ROWS = PkRow<T>::ROWS;  // rows per wave pass
     static_assert(PK_ROWS == 2, "the row part stages the pass's two rows as pairs");
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
         const int L = P / C, o = P % C;
         return L * C + ((((o >> 1) ^ (L & 7)) << 1) | (o & 1));
     };
-    // this lane's columns: col0 + u 64 E + lane E + e (u < 4, e < E); their
+    // this lane's columns: col0 + u 64 E + lane E + e (u < NL, e < E); their
     // labels (own-cluster sums) and staging slots of their sorted positions,
     // packed
     uint32_t labp[C / 4];
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
         };
         // the rows' segments in strip s: buffer loads whose range is empty
         // (so they read zeros) for a row right of the strip or past the segment
-        auto fetch = [&](const int32_t (&jj)[PK_ROWS], uint4 (&raw)[PK_ROWS][4]) {
+        auto fetch = [&](const int32_t (&jj)[PK_ROWS], uint4 (&raw)[PK_ROWS][NL]) {
 #pragma unroll
             for (int r = 0; r < PK_ROWS; ++r) {
                 const bool here = jj[r] >= 0 && ((uint32_t)jj[r] >> lgw) <= s32;
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
                 const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                     const_cast<T *>(row), (short)0, here ? (int)(W * sizeof(T)) : 0, 0x00020000);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < NL; ++u) {
                     const uint32_t off = (uint32_t)((u * kWave + lane) * E * sizeof(T));
                     const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
                     raw[r][u] = make_uint4(w[0], w[1], w[2], w[3]);
@@ -252,13 +258,13 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
             }
         };
         // one pass: the column part of the pass's rows, then their row part
-        auto process = [&](const uint4 (&raw)[PK_ROWS][4], const int32_t (&jr)[PK_ROWS], int32_t pr0) {
+        auto process = [&](const uint4 (&raw)[PK_ROWS][NL], const int32_t (&jr)[PK_ROWS], int32_t pr0) {
             bool up[PK_ROWS];
 #pragma unroll
             for (int r = 0; r < PK_ROWS; ++r) up[r] = jr[r] >= 0 && ((uint32_t)jr[r] >> lgw) < s32;
             // column part: the pass's rows added pairwise, then compensated
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < NL; ++u) {
                 float f[PK_ROWS][E];
 #pragma unroll
                 for (int r = 0; r < PK_ROWS; ++r) PkRow<T>::unpack(raw[r][u], f[r]);
@@ -276,7 +282,7 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
             // that are summed but not stored)
             if (!(up[0] || up[1])) return;  // wave-uniform
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < NL; ++u) {
                 float f0[E], f1[E];
                 PkRow<T>::unpack(raw[0][u], f0);
                 PkRow<T>::unpack(raw[1][u], f1);
@@ -361,7 +367,7 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
             pp += 4 * PK_ROWS;
         };
         auto live = [&]() { return pp < seg_end && ((uint32_t)jc[0] >> lgw) <= s32; };
-        uint4 rawA[PK_ROWS][4];
+        uint4 rawA[PK_ROWS][NL];
         while (live()) {
             fetch(jc, rawA);
             rows_at(pp + 8 * PK_ROWS, jq);

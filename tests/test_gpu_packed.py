@@ -1,5 +1,5 @@
 """The strip-packed symmetric K (the upper triangle in strips of W columns,
-W = 1024 for FP32 and 2048 for bfloat16) and the step that reads each stored
+W = 1024 for FP32 and bfloat16) and the step that reads each stored
 entry once, on the GPU.
 
 * layout: every stored entry of the packed K equals the dense K's entry bit
@@ -47,7 +47,7 @@ def to_dev(a):
 
 
 def lgw(kkm, k_store):
-    return 11 if k_store == kkm.BF16 else 10
+    return 10  # 1024-column strips for either storage type
 
 
 def row_offset(i, lg, ns):
