@@ -20,7 +20,7 @@ the dense-K figures are their own fields.
 Also reported:
 * time-to-converge of the plain FP32 form from the random labels (packed and
   dense K);
-* the mixed + learned form: BF16 Gram with K stored BF16 (80 GB), a feature
+* the mixed + learned form: BF16 Gram with K stored BF16 (strip-packed, 40.7 GB), a feature
   network trained beforehand on 10^7 kernel-value pairs of the same mixture
   (training time reported separately), the warm start (k-means++ and Lloyd in
   feature space, kkm_warm_start), then exact refinement to convergence; the
@@ -1066,22 +1066,23 @@ def main():
         log("reference from warm labels: %d iterations, J=%.6f" % (ref["iters"], ref["objective"]))
         del K
         torch.cuda.empty_cache()
-        K16 = kkm.alloc_kernel_matrix(n, kkm.BF16, dev)
+        K16 = kkm.alloc_kernel_matrix(n, kkm.BF16, dev)  # dense: k-means++ on K reads it
+        Kp16 = kkm.alloc_packed_kernel_matrix(n, kkm.BF16, dev)  # the refinement's K
         lab16 = torch.empty(n, dtype=torch.int32, device=dev)
 
         def mixed_learned():
             ta = time.perf_counter()
             wl, ch = warm_labels(kkm, w, params, Xd, useed)
             tb = time.perf_counter()
-            r = kkm.kkm_fit_ex(Xd, w.k, wl, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
-                               max_iter=300, check_convergence=True, K_ws=K16, labels_out=lab16)
+            r = kkm.kkm_fit_packed(Xd, w.k, wl, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
+                                   max_iter=300, check_convergence=True, K_ws=Kp16, labels_out=lab16)
             return tb - ta, ch, r
 
         def control():
-            # the same precision from the random labels
-            return kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16,
-                                  k_store=kkm.BF16, max_iter=300, check_convergence=True, K_ws=K16,
-                                  labels_out=lab16)
+            # the same precision and layout from the random labels
+            return kkm.kkm_fit_packed(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16,
+                                      k_store=kkm.BF16, max_iter=300, check_convergence=True,
+                                      K_ws=Kp16, labels_out=lab16)
 
         def kernel_seeded():
             # the non-learned warm start: k-means++ on the exact kernel matrix
@@ -1107,20 +1108,32 @@ def main():
 
         secs, (ws_s, ch, r) = timed_runs(torch, mixed_learned)
         ml_labels = lab16.cpu().numpy()
-        # per-iteration rate of the mixed form: 30 fixed iterations on the BF16 K
+        # per-iteration rate of the mixed form: 30 fixed iterations on the packed BF16 K,
+        # and on the dense BF16 K for comparison
         kkm.kkm_timing_enable(True)
-        kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
-                       max_iter=iters, check_convergence=False, K_ws=K16, labels_out=lab16)
+        kkm.kkm_fit_packed(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
+                           max_iter=iters, check_convergence=False, K_ws=Kp16, labels_out=lab16)
         torch.cuda.synchronize()
         tim16 = kkm.kkm_timing_read()
         it16 = float(np.median(iter_spans(kkm, 1, iters + 1)))
         kkm.kkm_timing_enable(False)
         sw16 = tim16["sweep"][0] / max(tim16["sweep"][1], 1)
-        g16 = tim16["gram"][0] / max(tim16["gram"][1], 1)
+        fold16 = tim16["fold"][0] / max(tim16["fold"][1], 1)
+        gp16 = tim16["gram"][0] / max(tim16["gram"][1], 1)
+        b16 = float(kkm.packed_elements(n, kkm.BF16)) * 2 + rowpart_bytes(n, w.k, 1024)
+        kkm.kkm_timing_enable(True)
+        kkm.kkm_fit_ex(Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
+                       max_iter=iters, check_convergence=False, K_ws=K16, labels_out=lab16)
+        torch.cuda.synchronize()
+        timd = kkm.kkm_timing_read()
+        itd16 = float(np.median(iter_spans(kkm, 1, iters + 1)))
+        kkm.kkm_timing_enable(False)
+        swd16 = timd["sweep"][0] / max(timd["sweep"][1], 1)
+        g16 = timd["gram"][0] / max(timd["gram"][1], 1)
         learned = {
             "seconds": secs, "warm_start_seconds": ws_s,
             "cheap_iters": ch, "exact_iters": r["iters"], "objective": r["objective"],
-            "gram": "bf16 mfma", "k_store": "bf16", "gram_ms": r["times_ms"][0],
+            "gram": "bf16 mfma", "k_store": "bf16 strip-packed", "gram_ms": r["times_ms"][0],
             "iter_ms": it16, "iters_per_s": 1e3 / it16,
             "ari_vs_fp32_from_same_warm_start": ari(ml_labels, ref_labels),
             "ari_vs_truth": ari(ml_labels, truth),
@@ -1133,8 +1146,12 @@ def main():
             # the plain run on the same dense K
             "exact_iters_saved_fp32": (plain_dense["iters"] - ref["iters"]) if plain_dense else None,
             "exact_iters_saved_bf16": rcn["iters"] - r["iters"],
-            "sweep_bf16": {"avg_ms": sw16, "achieved_gbs": float(n) * n * 2 / (sw16 * 1e-3) / 1e9,
-                           "frac_hbm": float(n) * n * 2 / (sw16 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "sweep_bf16": {"kernel": "packed_sweep<unsigned short>", "avg_ms": sw16,
+                           "algorithmic_bytes": b16, "achieved_gbs": b16 / (sw16 * 1e-3) / 1e9,
+                           "frac_hbm": b16 / (sw16 * 1e-3) / 1e9 / HBM_PEAK_GBS, "fold_ms": fold16},
+            "gram_bf16_packed_ms": gp16,
+            "dense_bf16": {"iter_ms": itd16, "sweep_ms": swd16,
+                           "sweep_frac_hbm": float(n) * n * 2 / (swd16 * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "gram_bf16": {"avg_ms": g16, "achieved_tflops": gram_flops / (g16 * 1e-3) / 1e12,
                           "frac_mfma": gram_flops / (g16 * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFS},
             "training": train_rep,
@@ -1150,7 +1167,7 @@ def main():
             "from same start %.4f; bf16 from random labels %.3f s (%d iterations)" % (
                 secs, ws_s, ch, r["iters"], learned["ari_vs_fp32_from_same_warm_start"], control_s,
                 rcn["iters"]))
-        del K16
+        del K16, Kp16
     else:
         del K
     torch.cuda.empty_cache()
