@@ -464,12 +464,12 @@ __global__ __launch_bounds__(256) void packed_fold(PkArgs a, Inst in, const int3
         float sm = 0.f, cm = 0.f;
         const int64_t cnt = a.ns - si - 1;
         int64_t u = 0;
-        for (; u + 8 <= cnt; u += 8) {  // eight loads in flight, added in order
-            float v[8];
+        for (; u + 16 <= cnt; u += 16) {  // sixteen loads in flight, added in order
+            float v[16];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) v[b] = src[(u + b) * sk];
+            for (int b = 0; b < 16; ++b) v[b] = src[(u + b) * sk];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
+            for (int b = 0; b < 16; ++b) {
                 float x, er;
                 two_sum(sm, v[b], x, er);
                 sm = x;
