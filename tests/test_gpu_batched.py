@@ -151,6 +151,38 @@ def test_subset_against_oracle(kkm):
         assert abs(r["objective"][b] - ref["objective"]) <= 1e-5 * scale, b
 
 
+def test_timed_configuration_subset_against_oracle(kkm):
+    """The configuration the benchmark times: BF16 product, K stored FP32, sweep
+    heights from the tuned table.  Each problem's run against the FP64 oracle's
+    run on the bfloat16-rounded points (the product's exact input; the GPU then
+    differs only by FP32 accumulation and summation order)."""
+    import torch
+    from quantref import bf16_round
+    from paper_2501_05587_amd import autotune
+    table = autotune.load(path=autotune.default_path("gfx950"))
+    specs = [s for s in SPECS if s[0] <= 3000]
+    probs, l0, host = build(kkm, specs, 900)
+    tuned = autotune.apply(probs, table, 0)
+    heights = [p["chunk_rows"] for p in tuned]
+    say("  tuned heights", heights)
+    assert any(h > 0 for h in heights)  # the table covers these sizes
+    r = kkm.kkm_fit_batched(tuned, l0, gram_prec=kkm.BF16, k_store=kkm.F32, max_iter=30)
+    torch.cuda.synchronize()
+    got = split(r["labels"].cpu().numpy(), specs)
+    for b, (n, d, k, kern, g, c0, deg) in enumerate(specs):
+        X, lab0 = host[b]
+        say("  oracle", b, specs[b], "height", heights[b])
+        K_or = oracle.kernel_matrix(bf16_round(X), KERNELS[kern], g, c0, deg)
+        ref = oracle.fit(K_or, k, lab0, 30)
+        recs = oracle.trajectory(K_or, k, lab0, 30)
+        scale = np.abs(np.diag(K_or)).sum() + np.abs(K_or).max() * n
+        tie = any((st["gap"] < 1e-6 * max(1.0, np.abs(K_or).max()) * 4).any() for _, st in recs)
+        if not tie:
+            np.testing.assert_array_equal(got[b], ref["labels"], err_msg="problem %d" % b)
+            assert r["iters"][b] == ref["iters"], b
+        assert abs(r["objective"][b] - ref["objective"]) <= 1e-5 * scale, b
+
+
 def test_chunk_rows_and_caller_workspace(kkm):
     """A tuned chunk length changes only the summation order; a workspace
     from the caller gives the same run as one the call allocates."""
