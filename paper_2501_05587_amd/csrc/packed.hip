@@ -432,9 +432,11 @@ __global__ __launch_bounds__(256) void pk_positions(Inst in, int32_t *pos) {
 // Row part of the step: for every point i and live cluster c, the bins of
 // row i over the strips right of its own (fixed order, compensated), added
 // to the partial sum of the cluster's first slot; a workgroup per 256 points
-// also adds its points' own-cluster values to that slot's own-cluster sum of
-// its 256-column group (point order).
-__global__ __launch_bounds__(256) void packed_fold(PkArgs a, Inst in, const int32_t *labels) {
+// (FOLD_THREADS threads, so that enough loads are in flight) also adds its
+// points' own-cluster values to that slot's own-cluster sum of its 256-column
+// group (point order).
+constexpr int FOLD_THREADS = 1024;
+__global__ __launch_bounds__(FOLD_THREADS) void packed_fold(PkArgs a, Inst in, const int32_t *labels) {
     __shared__ float own[256];
     __shared__ int32_t lab[256];
     if (*in.err != 0) return;
@@ -444,14 +446,14 @@ __global__ __launch_bounds__(256) void packed_fold(PkArgs a, Inst in, const int3
     const int64_t i0 = g * 256;
     const int tid = threadIdx.x;
     const int32_t *__restrict__ offsets = in.offsets;
-    {
+    if (tid < 256) {
         const int64_t i = i0 + tid;
         lab[tid] = (i < n) ? labels[i] : -1;
         own[tid] = 0.f;
     }
     __syncthreads();
     const int64_t pairs = (int64_t)256 * k;
-    for (int64_t t = tid; t < pairs; t += 256) {
+    for (int64_t t = tid; t < pairs; t += FOLD_THREADS) {
         const int64_t il = t / k;
         const int32_t cl = (int32_t)(t % k);
         const int64_t i = i0 + il;
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(256) void packed_fold(PkArgs a, Inst in, const int3
         if (lab[il] == cl) own[il] = s1;
     }
     __syncthreads();
-    for (int32_t cl = tid; cl < k; cl += 256) {
+    for (int32_t cl = tid; cl < k; cl += FOLD_THREADS) {
         const int64_t a0 = offsets[cl], a1 = offsets[cl + 1];
         if (a1 == a0) continue;
         float z = 0.f;
@@ -586,8 +588,8 @@ kkm_status pk_step(const void *K, int32_t k_store, const float *diagK, int64_t n
         const TimedSpan fold = timing_begin(TK_FOLD, st);
         hipLaunchKernelGGL(pk_positions, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, pos);
         KKM_HIP(hipGetLastError());
-        hipLaunchKernelGGL(packed_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, in,
-                           labels_in);
+        hipLaunchKernelGGL(packed_fold, dim3((unsigned)((n + 255) / 256)), dim3(FOLD_THREADS), 0, st,
+                           a, in, labels_in);
         KKM_HIP(hipGetLastError());
         timing_end(fold, st);
         return KKM_OK;
