@@ -36,7 +36,7 @@ template <> struct PkRow<float> {
     static constexpr int E = 4;     // elements per 16-byte load
     static constexpr int LOADS = 4; // 16-byte loads per lane and row: 16 columns
     static constexpr int ROWS = 2;  // rows per wave pass (4: two waves per SIMD instead of three, slower)
-    static constexpr int BLOCKS = 3;  // workgroups per CU (VGPR budget)
+    static constexpr int BLOCKS = 2;  // workgroups per CU (VGPR budget)
     static __device__ __forceinline__ void unpack(const uint4 &w, float (&v)[E]) {
         v[0] = __uint_as_float(w.x);
         v[1] = __uint_as_float(w.y);
@@ -317,12 +317,17 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // cluster t: its run's pieces, lane by lane
-            float *dst0 = a.R + (s * n + pr0) * k;  // the rows at positions pr0, pr0 + 1
-            float *dst1 = dst0 + k;
+            // cluster t: its run's pieces, lane by lane.  A row not left of the
+            // strip writes its sums to a scratch stretch past the bins instead
+            // of skipping the stores, so every pass issues the same stores and
+            // the wait for the next pass's rows, loaded before them, need not
+            // wait for them too.
+            float *const junk = a.R + ns * n * k;
+            float *dst0 = up[0] ? a.R + (s * n + pr0) * k : junk;  // positions pr0, pr0 + 1
+            float *dst1 = up[1] ? a.R + (s * n + pr0 + 1) * k : junk + k;
             const float2 *stg2 = reinterpret_cast<const float2 *>(stg);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < 2; ++h) {  // clusters lane, lane + 64 (k <= 128)
                 if (kWave * h >= k) break;  // wave-uniform
                 const int t = lane + kWave * h;
                 const int32_t np = (int32_t)(pc2n[h] >> 16);
@@ -344,16 +349,17 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
                     }
                 }
                 if (t < k) {
-                    if (up[0]) dst0[t] = v0;
-                    if (up[1]) dst1[t] = v1;
+                    dst0[t] = v0;
+                    dst1[t] = v1;
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         };
-        // row indices two passes ahead (loading the row segments a pass ahead
-        // as well measured no faster)
+        // row indices two passes ahead, row segments one pass ahead (issued
+        // before this pass's stores); the loop is taken twice per turn so that
+        // the two register sets swap roles without copies
         int32_t pp = p + wave * PK_ROWS;
         int32_t jc[PK_ROWS], jn[PK_ROWS], jq[PK_ROWS];
         rows_at(pp, jc);
@@ -367,11 +373,18 @@ __global__ __launch_bounds__(PK_THREADS, PkRow<T>::BLOCKS) void packed_sweep(PkA
             pp += 4 * PK_ROWS;
         };
         auto live = [&]() { return pp < seg_end && ((uint32_t)jc[0] >> lgw) <= s32; };
-        uint4 rawA[PK_ROWS][NL];
-        while (live()) {
-            fetch(jc, rawA);
+        uint4 rawA[PK_ROWS][NL], rawB[PK_ROWS][NL];
+        fetch(jc, rawA);
+        while (true) {
+            if (!live()) break;
+            fetch(jn, rawB);
             rows_at(pp + 8 * PK_ROWS, jq);
             process(rawA, jc, pp);
+            advance();
+            if (!live()) break;
+            fetch(jn, rawA);
+            rows_at(pp + 8 * PK_ROWS, jq);
+            process(rawB, jc, pp);
             advance();
         }
         // flush segment (q, c): the four waves' column sums, added in wave order
@@ -521,7 +534,8 @@ PkLayout pk_layout(int64_t n, int32_t k, int32_t k_store) {
     m.ns = packed_strips(n, m.lgw);
     m.g = inst_geometry(n, k, pk_chunk(n, m.ns));
     m.inst_bytes = inst_workspace_bytes(m.g);
-    m.rowpart_floats = (size_t)m.ns * (size_t)n * (size_t)k;  // by strip and position
+    // by strip and position, then 2 k floats the sweep writes for rows without sums
+    m.rowpart_floats = (size_t)m.ns * (size_t)n * (size_t)k + 2 * (size_t)k;
     m.n = n;
     return m;
 }
