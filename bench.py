@@ -321,7 +321,8 @@ def learned_c5_leg(kkm, torch, dev):
     draws, k=32, all to convergence: plain FP32 from random labels, the BF16
     form from the same random labels (the control), the BF16 form from the
     learned warm start, and the FP32 form from the warm start (the reference
-    for the result, ARI; and the exact iterations at equal precision)."""
+    for the result, ARI; and the exact iterations at equal precision); every
+    run on the strip-packed K."""
     import datagen
     w = datagen.WORKLOADS["learned100k"]
     X, truth = w.points()
@@ -329,23 +330,23 @@ def learned_c5_leg(kkm, torch, dev):
     ld = torch.from_numpy(w.labels0()).to(dev)
     n = w.n
     params, train_rep = train_feature_map(kkm, torch, w, dev)
-    K = kkm.alloc_kernel_matrix(n, kkm.F32, dev)
+    K = kkm.alloc_packed_kernel_matrix(n, kkm.F32, dev)
     lab = torch.empty(n, dtype=torch.int32, device=dev)
     useed = w.label_seed + 30003
 
-    plain_s, rp = timed_runs(torch, lambda: kkm.kkm_fit_ex(
+    plain_s, rp = timed_runs(torch, lambda: kkm.kkm_fit_packed(
         Xd, w.k, ld, w.kernel, w.gamma, max_iter=w.max_iter, check_convergence=True, K_ws=K,
         labels_out=lab))
     plain_labels = lab.cpu().numpy()
     warm, _ = warm_labels(kkm, w, params, Xd, useed)
-    ref = kkm.kkm_fit_ex(Xd, w.k, warm, w.kernel, w.gamma, max_iter=w.max_iter, check_convergence=True,
-                         K_ws=K, labels_out=lab)
+    ref = kkm.kkm_fit_packed(Xd, w.k, warm, w.kernel, w.gamma, max_iter=w.max_iter,
+                             check_convergence=True, K_ws=K, labels_out=lab)
     ref_labels = lab.cpu().numpy()
     del K
     torch.cuda.empty_cache()
-    K16 = kkm.alloc_kernel_matrix(n, kkm.BF16, dev)
+    K16 = kkm.alloc_packed_kernel_matrix(n, kkm.BF16, dev)
     lab16 = torch.empty(n, dtype=torch.int32, device=dev)
-    control_s, rc = timed_runs(torch, lambda: kkm.kkm_fit_ex(
+    control_s, rc = timed_runs(torch, lambda: kkm.kkm_fit_packed(
         Xd, w.k, ld, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16, max_iter=w.max_iter,
         check_convergence=True, K_ws=K16, labels_out=lab16))
     control_labels = lab16.cpu().numpy()
@@ -354,8 +355,8 @@ def learned_c5_leg(kkm, torch, dev):
         ta = time.perf_counter()
         wl, ch = warm_labels(kkm, w, params, Xd, useed)
         tb = time.perf_counter()
-        r = kkm.kkm_fit_ex(Xd, w.k, wl, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
-                           max_iter=w.max_iter, check_convergence=True, K_ws=K16, labels_out=lab16)
+        r = kkm.kkm_fit_packed(Xd, w.k, wl, w.kernel, w.gamma, gram_prec=kkm.BF16, k_store=kkm.BF16,
+                               max_iter=w.max_iter, check_convergence=True, K_ws=K16, labels_out=lab16)
         return tb - ta, ch, r
 
     secs, (ws_s, ch, r) = timed_runs(torch, learned_run)
@@ -366,6 +367,7 @@ def learned_c5_leg(kkm, torch, dev):
         "workload": "learned100k: fresh draws n=%d of the 32-component mixture in R^%d (sigma 0.5; "
                     "means seed 5000, training draws 5001, points 5002, labels 5003), k=%d, "
                     "gaussian gamma=1/%d" % (n, w.d, w.k, w.d),
+        "k_layout": "strip-packed upper triangle (every run)",
         "training": train_rep,
         "plain_fp32": {"seconds": plain_s, "iters": rp["iters"], "objective": rp["objective"],
                        "gram_ms": rp["times_ms"][0], "ari_vs_truth": ari(plain_labels, truth)},
