@@ -68,19 +68,20 @@ BF16_MFMA_PEAK_TFS = 2500.0
 # recorded value; otherwise the traffic is reported as null.
 TRAFFIC = {
     "packed_sweep": {"sources": ["csrc/packed.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
-                     "sha256": "3dd81dcb6d8c76e60040fcf089b91fca8e89d0a077994d437035d7fab94d11ce",
-                     "n": 200000, "fetch_kib": 39630000.0, "write_kib": 4981000.0,
+                     "sha256": "9c4c2f548bbb2b7e4a422e02d3651094544331fbe9c7561a14b016975b58ea99",
+                     "n": 200000, "fetch_kib": 39626200.0, "write_kib": 4982190.0,
                      "fetch_scale": 1.9999, "write_scale": 1.0},
     "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
-                       "sha256": "5144509e16a16636ce2b3fd0a1c8369bef350864dc390967a6a6a465951e62dc",
-                       "n": 200000, "fetch_kib": 78170000.0, "write_kib": 89550.0,
+                       "sha256": "c637e03921a67e79aae60f3292840e1306a0850dc58cef5bad95c3d92e7f3e0d",
+                       "n": 200000, "fetch_kib": 78172500.0, "write_kib": 89559.1,
                        "fetch_scale": 1.9999, "write_scale": 1.0},
     "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_f32.hip", "csrc/gram_tile.h",
                                   "csrc/kkm_common.h"],
-                      "sha256": "7b766ecfcd9198c14ac729c43d4c00644e90efa8b0e7ee4356a215007a00c917",
-                      "n": 200000, "fetch_kib": 147900000.0, "write_kib": 156300000.0,
+                      "sha256": "1e5cf15c1838e226ebba54dbf3569a384f2c7e210ec336da17f3d6da281dd4b9",
+                      "n": 200000, "fetch_kib": 148595000.0, "write_kib": 156251000.0,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }
+
 
 
 # feature network and its training (learned warm start)
