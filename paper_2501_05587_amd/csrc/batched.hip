@@ -282,6 +282,11 @@ kkm_status check_instances(const kkm_instance *inst, int32_t count, int32_t gram
             set_error("kkm_fit_batched: problem %d has k=%d > KKM_MAX_K=%d", b, p.k, KKM_MAX_K);
             return KKM_ERR_UNSUPPORTED;
         }
+        if (gram_prec != KKM_F32 && !lowp_rows_fit(p.d, gram_prec)) {
+            set_error("kkm_fit_batched: problem %d has d=%lld, too large for the BF16 / FP8 "
+                      "product's 32-bit row ranges", b, (long long)p.d);
+            return KKM_ERR_UNSUPPORTED;
+        }
         if (p.chunk_rows < 0 || p.chunk_rows > (1 << 20)) {
             set_error("kkm_fit_batched: problem %d has chunk_rows=%d outside [0, 2^20]", b,
                       p.chunk_rows);

@@ -84,6 +84,11 @@ kkm_status gram_launch(const float *X, int64_t n, int64_t d, int64_t ldx, int32_
         set_error("kkm_gram: workspace of %zu bytes is smaller than %zu", ws_bytes, need);
         return KKM_ERR_NOMEM;
     }
+    if (gram_prec != KKM_F32 && !lowp_rows_fit(d, gram_prec)) {
+        set_error("kkm_gram: d=%lld is too large for the BF16 / FP8 product's 32-bit row ranges",
+                  (long long)d);
+        return KKM_ERR_UNSUPPORTED;
+    }
     Carver c(ws);
     float *nrm = c.take<float>((size_t)n);
     Epi e;

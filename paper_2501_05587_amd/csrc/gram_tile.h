@@ -698,6 +698,13 @@ inline int64_t padded_d(int64_t d, int32_t gram_prec) {
     return (d + per - 1) / per * per;
 }
 
+// Whether a tile's 128 rounded rows fit one 32-bit buffer range (the product
+// reads its operand rows through such ranges).
+inline bool lowp_rows_fit(int64_t d, int32_t gram_prec) {
+    const int64_t eb = (gram_prec == KKM_BF16) ? 2 : 1;
+    return (int64_t)GM * padded_d(d, gram_prec) * eb <= (int64_t)0x7fffffff;
+}
+
 // One 128 x 128 tile (bi, bj) of the product and its epilogue, by the 256
 // threads of a workgroup, staging through `lds`.
 template <int PREC, typename OUT, bool FULL = false, bool DB = true>

@@ -46,6 +46,11 @@ def test_argument_validation_without_device_work(lib):
     # ldx < d, ldk < n
     assert lib.kkm_gram(fake, 8, 4, 3, 2, 1.0, 0.0, 1, 0, 0, fake, 8, fake, None, 0, None) == -1
     assert lib.kkm_gram(fake, 8, 4, 4, 2, 1.0, 0.0, 1, 0, 0, fake, 7, fake, None, 0, None) == -1
+    # a BF16 product whose 128 rounded rows pass a 32-bit buffer range
+    big_d = 9_000_000
+    assert lib.kkm_gram(fake, 8, big_d, big_d, 2, 1.0, 0.0, 1, 1, 0, fake, 8, fake, fake,
+                        ctypes.c_size_t(1 << 40), None) == -5
+    assert b"too large" in lib.kkm_last_error()
     # kkm_iterate: k > n, aliasing, k too large
     z = None
     assert lib.kkm_iterate(fake, 0, 8, fake, 8, 9, fake, 0, vp(32), fake, fake, fake, z, z, z, 0, z) == -1
