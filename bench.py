@@ -77,8 +77,8 @@ TRAFFIC = {
                        "fetch_scale": 1.9999, "write_scale": 1.0},
     "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_f32.hip", "csrc/gram_tile.h",
                                   "csrc/kkm_common.h"],
-                      "sha256": "1e5cf15c1838e226ebba54dbf3569a384f2c7e210ec336da17f3d6da281dd4b9",
-                      "n": 200000, "fetch_kib": 148595000.0, "write_kib": 156251000.0,
+                      "sha256": "0222f3a5cc8703266ae98bff79ed73cd0bd9faf9bcb3798738ef3f643fa44b13",
+                      "n": 200000, "fetch_kib": 148194033.5, "write_kib": 156250880.9,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }
 
