@@ -147,6 +147,48 @@ __device__ __forceinline__ void store_rows(const Epi &e, const float *T, int64_t
     }
 }
 
+// The whole tile staged as bfloat16 (bfloat16 K and the half-tile epilogue:
+// it fits where half of it fits as FP32): row stride in elements, bytes.
+constexpr int TS16 = GM + 8;
+constexpr size_t epi_lds_bytes_bf16 = sizeof(uint16_t) * GM * TS16;
+
+// The bfloat16 tile T16 to K[row0 + r][col0 .. col0 + 127], skipping rows and
+// columns at or past n: each thread stores 8 columns (16 bytes) of every
+// sixteenth row, reading 4 rows from LDS before it waits.
+__device__ __forceinline__ void store_rows_bf16(const Epi &e, const uint16_t *T16, int64_t row0,
+                                                int64_t col0) {
+    const int tid = threadIdx.x;
+    const int c8 = (tid & 15) * 8;
+    const int64_t gj0 = col0 + c8;
+    if (gj0 >= e.n) return;
+    const bool full = gj0 + 7 < e.n;
+    uint16_t *K16 = static_cast<uint16_t *>(e.K);
+    constexpr int B = 4;
+#pragma unroll
+    for (int h = 0; h < GM / (16 * B); ++h) {
+        uint4 w[B];
+#pragma unroll
+        for (int it = 0; it < B; ++it)
+            w[it] = *reinterpret_cast<const uint4 *>(T16 + ((tid >> 4) + 16 * (B * h + it)) * TS16 + c8);
+#pragma unroll
+        for (int it = 0; it < B; ++it) {
+            const int64_t gi = row0 + (tid >> 4) + 16 * (B * h + it);
+            if (gi >= e.n) continue;
+            uint16_t *dst = K16 + k_index(e, gi, gj0);
+            if (full && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+                typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+                const u32x4 v = {w[it].x, w[it].y, w[it].z, w[it].w};
+                __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(dst));
+            } else {
+                const uint32_t q[4] = {w[it].x, w[it].y, w[it].z, w[it].w};
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (gj0 + r < e.n) dst[r] = (uint16_t)((r & 1) ? (q[r >> 1] >> 16) : (q[r >> 1] & 0xFFFFu));
+            }
+        }
+    }
+}
+
 // The squared norms (and FP8 row scales) of a tile's 128 rows and 128
 // columns, staged in LDS when the tile starts so that their loads overlap the
 // product: [0, 128) rows m0.., [128, 256) rows n0...  Needs a barrier before
@@ -337,6 +379,48 @@ __device__ __forceinline__ void epilogue(const Epi &e, f32x16 (&acc)[2][2], int6
                             const f32x2 f = {acc[mi][ni][2 * t], acc[mi][ni][2 * t + 1]};
                             kb[mi][ni][t] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
                         }
+            }
+            if constexpr (PACK && HALVES == 2) {
+                // the whole tile staged as bfloat16: one round per pass, each
+                // lane's four rows of a column leaving as one 8-byte LDS write
+                // in the transposed pass
+                uint16_t *T16 = reinterpret_cast<uint16_t *>(T);
+                if (mirror_stored(e, m0, n0)) {  // uniform: a packed K outside a strip skips it
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni) {
+                            const int jj = wc * 64 + ni * 32 + l32;
+#pragma unroll
+                            for (int rg = 0; rg < 4; ++rg) {
+                                const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+                                *reinterpret_cast<uint2 *>(T16 + jj * TS16 + ii0) =
+                                    make_uint2(kb[mi][ni][2 * rg], kb[mi][ni][2 * rg + 1]);
+                            }
+                        }
+                    __syncthreads();
+                    store_rows_bf16(e, T16, n0, m0);  // K[n0 + jj][m0 ..]; m0 + 127 < n0
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni) {
+                        const int jj = wc * 64 + ni * 32 + l32;
+#pragma unroll
+                        for (int rg = 0; rg < 4; ++rg) {
+                            const int ii0 = wr * 64 + mi * 32 + 8 * rg + 4 * half;
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const uint32_t w = kb[mi][ni][(4 * rg + r) >> 1];
+                                T16[(ii0 + r) * TS16 + jj] = (uint16_t)((r & 1) ? (w >> 16) : (w & 0xFFFFu));
+                            }
+                        }
+                    }
+                __syncthreads();
+                store_rows_bf16(e, T16, m0, n0);  // every row exists; columns may pass n
+                __syncthreads();
+                return;
             }
             auto kept = [&](int mi, int ni, int idx) -> float {
                 if constexpr (PACK) {
@@ -826,6 +910,8 @@ __device__ __forceinline__ void lowp_tile(const LowpTile &a, int64_t bi, int64_t
         }
     }
     static_assert(sizeof(lds.op) >= epi_lds_bytes(DB ? 1 : 2), "epilogue tile does not fit");
+    static_assert(DB || sizeof(OUT) != 2 || sizeof(lds.op) >= epi_lds_bytes_bf16,
+                  "bfloat16 epilogue tile does not fit");
     epilogue<OUT, FULL, DB ? 1 : 2>(a.e, acc, m0, n0, bi == bj, wr, wc, lane,
                                     reinterpret_cast<float *>(&lds.op[0][0][0]), lds.rn, lds.rs);
 }
