@@ -77,8 +77,8 @@ TRAFFIC = {
                        "fetch_scale": 1.9999, "write_scale": 1.0},
     "gram_f32_mfma": {"sources": ["csrc/gram.hip", "csrc/gram_f32.hip", "csrc/gram_tile.h",
                                   "csrc/kkm_common.h"],
-                      "sha256": "0222f3a5cc8703266ae98bff79ed73cd0bd9faf9bcb3798738ef3f643fa44b13",
-                      "n": 200000, "fetch_kib": 148194033.5, "write_kib": 156250880.9,
+                      "sha256": "1920afcb061279bf55ae100518467f6a630c38de26a57e6a3ac2651cdb6d8c45",
+                      "n": 200000, "fetch_kib": 150314010.6, "write_kib": 156250877.6,
                       "fetch_scale": 1.9999, "write_scale": 1.0},
 }
 
