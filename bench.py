@@ -68,8 +68,8 @@ BF16_MFMA_PEAK_TFS = 2500.0
 # recorded value; otherwise the traffic is reported as null.
 TRAFFIC = {
     "packed_sweep": {"sources": ["csrc/packed.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
-                     "sha256": "9c4c2f548bbb2b7e4a422e02d3651094544331fbe9c7561a14b016975b58ea99",
-                     "n": 200000, "fetch_kib": 39626200.0, "write_kib": 4982190.0,
+                     "sha256": "66383f026b912c68650d64dd811367e16957e8509415de7ca5317ccb281e23c9",
+                     "n": 200000, "fetch_kib": 39621828.6, "write_kib": 4963045.4,
                      "fetch_scale": 1.9999, "write_scale": 1.0},
     "spmm_row_sweep": {"sources": ["csrc/iterate.hip", "csrc/iterate.h", "csrc/kkm_common.h"],
                        "sha256": "c637e03921a67e79aae60f3292840e1306a0850dc58cef5bad95c3d92e7f3e0d",
